@@ -1,0 +1,207 @@
+/*
+ * ptap.h -- C ABI of the MI355X (gfx950) library for the sparse triple product
+ *
+ *     C = P^T A P,   A: n x n,  P: n x m,  C: m x m   (Section 3, Eq. tripleproduct)
+ *
+ * built with the all-at-once and merged all-at-once algorithms (Section 3, Alg. 7-10):
+ * each row R_I = A(I,:) P of the product AP is formed in a hash accumulator and folded at
+ * once into C by the outer product P(I,:) (x) R_I (Eq. allatonceoutproduct), so that neither
+ * AP nor P^T is ever stored.  The two-step method (Alg. 5-6: AP and P^T stored explicitly,
+ * then P^T (AP)) is provided beside it as the memory and speed comparison.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are CSR: int32 row pointers (n_rows + 1 entries, rowptr[0] = 0), int32 column
+ *    indices sorted strictly ascending within each row, double values.  Every matrix
+ *    pointer is a DEVICE pointer unless stated otherwise.
+ *  - The computation is split as in Section 2: a symbolic phase that fixes the pattern of C
+ *    with no floating point, and a numeric phase that can be repeated with new values on
+ *    the same patterns (the paper runs one symbolic and eleven numerics, Section 4.1).
+ *  - The pattern of C is the structural product: (i, j) is stored whenever some I, J have
+ *    P(I,i), A(I,J) and P(J,j) stored, whatever their values.  Rows of C are sorted.
+ *  - Every launch is enqueued on the caller's stream.  ptap_plan_create (with validation)
+ *    and ptap_symbolic synchronise that stream; ptap_numeric, ptap_backward and the batch
+ *    launch never do.
+ *  - Every entry point returns a ptap_status; no C++ exception crosses this boundary.
+ *    Plans are not thread-safe: calls on one plan must not overlap.
+ *  - Device workspace is obtained from the caller's allocator (or hipMalloc when none is
+ *    given) and counted in ptap_plan_stats.
+ */
+#ifndef PTAP_H_
+#define PTAP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ptap_status {
+  PTAP_OK = 0,
+  PTAP_ERR_INPUT = 1,       /* malformed CSR, shape mismatch, bad option, NULL argument */
+  PTAP_ERR_TOO_LARGE = 2,   /* a count would overflow int32 indexing */
+  PTAP_ERR_OOM = 3,         /* the allocator returned NULL; the plan is left unchanged */
+  PTAP_ERR_HIP = 4,         /* a HIP runtime call failed; see ptap_last_hip_error */
+  PTAP_ERR_STATE = 5,       /* call out of order (e.g. numeric before symbolic) */
+  PTAP_ERR_UNSUPPORTED = 6  /* option combination not provided */
+} ptap_status;
+
+/* Algorithm choice (the paper's "allatonce", "merged" and "two-step", Section 4). */
+typedef enum ptap_algo {
+  PTAP_ALLATONCE = 0, /* Alg. 7/8: pass 1 over rows with off-block P entries, pass 2 over
+                         rows with on-block P entries; R_I is formed again in pass 2 */
+  PTAP_MERGED = 1,    /* Alg. 9/10: one pass, R_I formed once and folded into both parts */
+  PTAP_TWOSTEP = 2    /* Alg. 5/6: stored AP and P^T, then the row-wise product P^T (AP) */
+} ptap_algo;
+
+/* How the outer product P(I,:) (x) R_I is added into C (all-at-once and merged only). */
+typedef enum ptap_fold {
+  PTAP_FOLD_AUTO = 0,   /* the owner fold (the faster one on MI355X) */
+  PTAP_FOLD_ATOMIC = 1, /* fine-row sweep; device-wide FP64 atomic adds into C at the slot of
+                           each (i, j), found through C's column list of row i */
+  PTAP_FOLD_OWNER = 2   /* coarse-row ownership: a workgroup owns a contiguous tile of C rows,
+                           visits the fine rows I with P(I,i) stored for i in the tile (found
+                           through P's column index lists, i.e. Eq. allatoncerow), forms each
+                           R_I and accumulates in on-chip memory; no global atomics */
+} ptap_fold;
+
+/* Allocator for device workspace.  alloc returns a device pointer or NULL; release frees a
+ * pointer returned by alloc.  ctx is passed through unchanged. */
+typedef struct ptap_allocator {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, size_t bytes, void* ctx);
+  void* ctx;
+} ptap_allocator;
+
+typedef struct ptap_options {
+  int32_t algo;          /* ptap_algo */
+  int32_t fold;          /* ptap_fold; ignored by PTAP_TWOSTEP */
+  int32_t nblocks;       /* K >= 1: virtual ownership blocks.  Fine rows and coarse columns are
+                            split into K contiguous ranges as in the 1D row partition of
+                            Section 2 (Eq. partition); P(I,i) is "diagonal" (P_d) when I and i
+                            fall in the same block and "off-diagonal" (P_o) otherwise.  K = 1
+                            makes P_o empty, so all-at-once and merged coincide. */
+  int32_t tile_entries;  /* owner fold: maximum C entries per tile held on chip (0: default) */
+  int32_t hash_slots;    /* 0: automatic.  Otherwise the largest on-chip hash table, in slots
+                            (power of two >= 64); longer rows use tables in device memory.
+                            Setting it low forces the spill path (used by tests). */
+  int32_t validate;      /* nonzero: check both CSR inputs at plan creation (one sync) */
+  int32_t xcd_remap;     /* nonzero: map workgroups to tiles so that consecutive tiles run on
+                            the same XCD (shared L2 for their common fine rows) */
+  int32_t backward;      /* nonzero: also prepare the adjoint (ptap_backward) at symbolic time */
+  int32_t reserved[8];
+} ptap_options;
+
+typedef struct ptap_stats {
+  int64_t nnz_C;
+  int64_t nnz_AP;              /* two-step: entries of the stored auxiliary AP; else 0 */
+  int64_t workspace_bytes;     /* device bytes held by the plan now (includes C's pattern) */
+  int64_t peak_bytes;          /* high-water mark of the plan's device allocations */
+  int64_t pattern_bytes;       /* bytes of C's row pointers and column indices */
+  int64_t rows_formed;         /* AP rows formed by one numeric call (with recomputation) */
+  int64_t rows_needed;         /* fine rows with a nonempty row of P (formed once each at best) */
+  int64_t fold_terms;          /* products P(I,i) * R_I(j) added into C by one numeric call */
+  int32_t n_tiles;             /* owner fold: number of C-row tiles */
+  int32_t fold_used;           /* ptap_fold actually used */
+  int32_t algo;                /* ptap_algo of the plan */
+  int32_t nblocks;
+  int64_t reserved[8];
+} ptap_stats;
+
+typedef struct ptap_plan ptap_plan;
+typedef struct ptap_batch ptap_batch;
+
+/* Fill *opts with the defaults: merged, owner fold, K = 1, automatic sizes, validation on. */
+void ptap_options_default(ptap_options* opts);
+
+/*
+ * Create a plan for C = P^T A P on the patterns of A (n x n, A_nnz entries) and P (n x m,
+ * P_nnz entries).  The pattern arrays are caller-owned device arrays and must stay alive and
+ * unchanged for the life of the plan.  opts may be NULL (defaults), alloc may be NULL
+ * (hipMalloc/hipFree).  On success *out owns a host object released by ptap_plan_destroy.
+ * Errors: PTAP_ERR_INPUT (NULL pointer, n or m negative, nnz mismatch, unsorted, duplicate or
+ * out-of-range columns, non-monotone row pointers, bad options), PTAP_ERR_TOO_LARGE,
+ * PTAP_ERR_OOM, PTAP_ERR_HIP.
+ */
+ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_t* A_rowptr,
+                             const int32_t* A_col, int64_t A_nnz, const int32_t* P_rowptr,
+                             const int32_t* P_col, int64_t P_nnz, const ptap_options* opts,
+                             const ptap_allocator* alloc, hipStream_t stream);
+
+/*
+ * Symbolic phase (Section 2; Alg. 7/9 for all-at-once and merged, Alg. 5 for two-step):
+ * computes and keeps the pattern of C and every index structure the numeric phase needs.
+ * Synchronises the stream (it reads nnz(C) and the row classes on the host).
+ * Errors: PTAP_ERR_STATE if already done, PTAP_ERR_TOO_LARGE, PTAP_ERR_OOM, PTAP_ERR_HIP.
+ */
+ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream);
+
+/* Pointers to the plan-owned pattern of C (device arrays of m+1 and nnz(C) entries).  Valid
+ * until ptap_plan_destroy.  Errors: PTAP_ERR_STATE before symbolic. */
+ptap_status ptap_get_pattern(const ptap_plan* plan, int64_t* nnz_C, const int32_t** C_rowptr,
+                             const int32_t** C_col);
+
+/*
+ * Numeric phase (Alg. 8 all-at-once, Alg. 10 merged, Alg. 6 two-step): writes the nnz(C)
+ * values of C, in the order of the pattern, into the caller's device array C_val.  A_val and
+ * P_val hold the values of A and P in the order of their patterns.  Asynchronous on the
+ * stream; allocates nothing.  Inputs must not alias C_val.
+ * Errors: PTAP_ERR_STATE before symbolic, PTAP_ERR_INPUT (NULL), PTAP_ERR_HIP.
+ */
+ptap_status ptap_numeric(ptap_plan* plan, const double* A_val, const double* P_val, double* C_val,
+                         hipStream_t stream);
+
+/*
+ * Adjoint of the numeric phase.  Given dC = dL/dC on the pattern of C, writes
+ *   dA = P dC P^T                 restricted to the pattern of A  (A_nnz values), and
+ *   dP = A P dC^T + A^T P dC      restricted to the pattern of P  (P_nnz values),
+ * the derivatives of L with respect to the stored entries of A and P.  Either output may be
+ * NULL to skip it.  Rows of AP are formed again, never stored.  Outputs are overwritten.
+ * Asynchronous; allocates nothing.  Errors: as ptap_numeric.
+ */
+ptap_status ptap_backward(ptap_plan* plan, const double* A_val, const double* P_val,
+                          const double* dC_val, double* dA_val, double* dP_val,
+                          hipStream_t stream);
+
+/* Statistics of the plan (host struct filled by the call). */
+ptap_status ptap_plan_stats(const ptap_plan* plan, ptap_stats* out);
+
+/* Release the plan and all its device workspace (through the plan's allocator).  Accepts
+ * NULL.  The caller must make sure no work of the plan is still running. */
+void ptap_plan_destroy(ptap_plan* plan);
+
+/*
+ * Batched numeric over several plans (levels of a hierarchy or independent problems).
+ * plans[k] must have finished its symbolic phase; the plans stay owned by the caller and
+ * must outlive the batch.  level[k] orders the work: every product with level L runs after
+ * every product with a smaller level (a coarse level's A is the previous level's C), and
+ * products of one level run together in one persistent launch.  level may be NULL (all 0).
+ * The batch records its launches once into a HIP graph at the first ptap_batch_numeric call
+ * and replays the graph afterwards; pointer arguments must therefore stay the same on every
+ * call (their contents may change).
+ * Errors: PTAP_ERR_INPUT, PTAP_ERR_STATE (a plan without symbolic, two-step plans),
+ * PTAP_ERR_OOM, PTAP_ERR_HIP.
+ */
+ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const int32_t* level,
+                              int32_t count, const ptap_allocator* alloc, hipStream_t stream);
+
+/* A_vals[k], P_vals[k], C_vals[k]: host arrays of device pointers, one per plan. */
+ptap_status ptap_batch_numeric(ptap_batch* batch, const double* const* A_vals,
+                               const double* const* P_vals, double* const* C_vals,
+                               hipStream_t stream);
+
+void ptap_batch_destroy(ptap_batch* batch);
+
+/* Static description of a status code.  Never NULL. */
+const char* ptap_status_string(ptap_status status);
+
+/* The hipError_t of the last failing HIP call made by the library on this thread (0 if none). */
+int32_t ptap_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTAP_H_ */

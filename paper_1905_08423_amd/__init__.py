@@ -1,0 +1,375 @@
+"""Python binding of libptap.so, the MI355X library for C = P^T A P (all-at-once, merged
+all-at-once and two-step; Section 3 of the paper).
+
+The functions named ptap_* are thin ctypes marshals of the C ABI in include/ptap.h, with the
+same names and arguments.  Every computation runs in the library's HIP kernels; PyTorch only
+provides device memory (through the plan allocator) and the current stream.  If the library
+is not built, loading fails loudly: there is no fallback.
+
+Higher-level helpers: Plan (owns the pattern tensors and the plan handle), ptap() for a
+one-shot product, and PtAPFunction, a torch.autograd.Function whose backward calls
+ptap_backward.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptap.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ptap.h")
+
+# ptap_status
+PTAP_OK, PTAP_ERR_INPUT, PTAP_ERR_TOO_LARGE, PTAP_ERR_OOM, PTAP_ERR_HIP, PTAP_ERR_STATE, PTAP_ERR_UNSUPPORTED = range(7)
+# ptap_algo
+PTAP_ALLATONCE, PTAP_MERGED, PTAP_TWOSTEP = range(3)
+# ptap_fold
+PTAP_FOLD_AUTO, PTAP_FOLD_ATOMIC, PTAP_FOLD_OWNER = range(3)
+
+ALGOS = {"allatonce": PTAP_ALLATONCE, "merged": PTAP_MERGED, "twostep": PTAP_TWOSTEP}
+FOLDS = {"auto": PTAP_FOLD_AUTO, "atomic": PTAP_FOLD_ATOMIC, "owner": PTAP_FOLD_OWNER}
+
+
+class ptap_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("release", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+                ("ctx", ctypes.c_void_p)]
+
+
+class ptap_options(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("fold", ctypes.c_int32), ("nblocks", ctypes.c_int32),
+                ("tile_entries", ctypes.c_int32), ("hash_slots", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("backward", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class ptap_stats(ctypes.Structure):
+    _fields_ = [("nnz_C", ctypes.c_int64), ("nnz_AP", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("pattern_bytes", ctypes.c_int64), ("rows_formed", ctypes.c_int64),
+                ("rows_needed", ctypes.c_int64), ("fold_terms", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int32), ("fold_used", ctypes.c_int32),
+                ("algo", ctypes.c_int32), ("nblocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int64 * 8)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_SIGNATURES = {
+    "ptap_options_default": (None, [ctypes.POINTER(ptap_options)]),
+    "ptap_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, _vp, _vp, _i64, _vp, _vp, _i64,
+                                        ctypes.POINTER(ptap_options), ctypes.POINTER(ptap_allocator), _vp]),
+    "ptap_symbolic": (ctypes.c_int, [_vp, _vp]),
+    "ptap_get_pattern": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "ptap_numeric": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ptap_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ptap_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ptap_stats)]),
+    "ptap_plan_destroy": (None, [_vp]),
+    "ptap_batch_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i32), _i32,
+                                         ctypes.POINTER(ptap_allocator), _vp]),
+    "ptap_batch_numeric": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+    "ptap_batch_destroy": (None, [_vp]),
+    "ptap_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ptap_last_hip_error": (_i32, []),
+}
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/ptap.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ptap_[a-z_]+)\s*\(", text)) - {"ptap_status", "ptap_algo", "ptap_fold"})
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libptap.so and declare the C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run python -m paper_1905_08423_amd.build "
+                               "(there is no fallback implementation)")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class PtapError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load_library()
+        msg = lib.ptap_status_string(status).decode()
+        hip = lib.ptap_last_hip_error()
+        super().__init__(f"{where}: {msg} (status {status}, hip error {hip})")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != PTAP_OK:
+        raise PtapError(status, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        if not torch.cuda.is_available():
+            return None  # argument checks only; nothing can run without a device
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------------------------
+# Thin marshals with the C names
+# ---------------------------------------------------------------------------------------------
+
+def ptap_options_default() -> ptap_options:
+    o = ptap_options()
+    load_library().ptap_options_default(ctypes.byref(o))
+    return o
+
+
+def ptap_plan_create(n, m, A_rowptr, A_col, A_nnz, P_rowptr, P_col, P_nnz, opts=None, alloc=None,
+                     stream=None):
+    h = ctypes.c_void_p()
+    st = load_library().ptap_plan_create(ctypes.byref(h), n, m, _ptr(A_rowptr), _ptr(A_col), A_nnz,
+                                         _ptr(P_rowptr), _ptr(P_col), P_nnz,
+                                         ctypes.byref(opts) if opts is not None else None,
+                                         ctypes.byref(alloc) if alloc is not None else None,
+                                         _stream(stream))
+    return st, h
+
+
+def ptap_symbolic(plan, stream=None):
+    return load_library().ptap_symbolic(plan, _stream(stream))
+
+
+def ptap_get_pattern(plan):
+    nnz = _i64()
+    rp = ctypes.c_void_p()
+    col = ctypes.c_void_p()
+    st = load_library().ptap_get_pattern(plan, ctypes.byref(nnz), ctypes.byref(rp), ctypes.byref(col))
+    return st, nnz.value, rp.value, col.value
+
+
+def ptap_numeric(plan, A_val, P_val, C_val, stream=None):
+    return load_library().ptap_numeric(plan, _ptr(A_val), _ptr(P_val), _ptr(C_val), _stream(stream))
+
+
+def ptap_backward(plan, A_val, P_val, dC_val, dA_val, dP_val, stream=None):
+    return load_library().ptap_backward(plan, _ptr(A_val), _ptr(P_val), _ptr(dC_val), _ptr(dA_val),
+                                        _ptr(dP_val), _stream(stream))
+
+
+def ptap_plan_stats(plan):
+    s = ptap_stats()
+    st = load_library().ptap_plan_stats(plan, ctypes.byref(s))
+    return st, s
+
+
+def ptap_plan_destroy(plan):
+    load_library().ptap_plan_destroy(plan)
+
+
+def ptap_batch_create(plans, levels=None, alloc=None, stream=None):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * len(plans))(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    lv = None if levels is None else (ctypes.c_int32 * len(plans))(*levels)
+    st = load_library().ptap_batch_create(ctypes.byref(h), arr, lv, len(plans),
+                                          ctypes.byref(alloc) if alloc is not None else None,
+                                          _stream(stream))
+    return st, h
+
+
+def ptap_batch_numeric(batch, A_vals, P_vals, C_vals, stream=None):
+    k = len(A_vals)
+    mk = lambda ts: (ctypes.c_void_p * k)(*[t.data_ptr() for t in ts])  # noqa: E731
+    return load_library().ptap_batch_numeric(batch, mk(A_vals), mk(P_vals), mk(C_vals), _stream(stream))
+
+
+def ptap_batch_destroy(batch):
+    load_library().ptap_batch_destroy(batch)
+
+
+def ptap_status_string(status):
+    return load_library().ptap_status_string(status).decode()
+
+
+def ptap_last_hip_error():
+    return load_library().ptap_last_hip_error()
+
+
+# ---------------------------------------------------------------------------------------------
+# Torch-backed allocator: every plan buffer is a torch tensor, so torch's memory statistics
+# see the plan's workspace.
+# ---------------------------------------------------------------------------------------------
+class TorchAllocator:
+    def __init__(self, device=None):
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.live = {}
+        alloc_t = ptap_allocator._fields_[0][1]
+        release_t = ptap_allocator._fields_[1][1]
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            except RuntimeError:
+                return None
+            self.live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _release(ptr, nbytes, ctx):
+            self.live.pop(ptr, None)
+
+        self.c_alloc = alloc_t(_alloc)
+        self.c_release = release_t(_release)
+        self.struct = ptap_allocator(self.c_alloc, self.c_release, None)
+
+    @property
+    def held_bytes(self):
+        return sum(t.numel() for t in self.live.values())
+
+
+class Plan:
+    """A plan for C = P^T A P on fixed patterns of A and P (device tensors).
+
+    algo: "allatonce" | "merged" | "twostep"; fold: "auto" | "atomic" | "owner"; nblocks: K.
+    The symbolic phase runs at construction; numeric() may be called many times."""
+
+    def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
+                 nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
+                 backward=False, allocator=None, stream=None):
+        load_library()
+        self.n, self.m = int(n), int(m)
+        self.A_rowptr, self.A_col = A_rowptr, A_col
+        self.P_rowptr, self.P_col = P_rowptr, P_col
+        self.A_nnz, self.P_nnz = int(A_col.numel()), int(P_col.numel())
+        self.allocator = allocator if allocator is not None else TorchAllocator(A_rowptr.device)
+        o = ptap_options_default()
+        o.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
+        o.fold = FOLDS[fold] if isinstance(fold, str) else int(fold)
+        o.nblocks = int(nblocks)
+        o.tile_entries = int(tile_entries)
+        o.hash_slots = int(hash_slots)
+        o.validate = 1 if validate else 0
+        o.xcd_remap = 1 if xcd_remap else 0
+        o.backward = 1 if backward else 0
+        self.options = o
+        self.handle = None
+        st, h = ptap_plan_create(self.n, self.m, A_rowptr, A_col, self.A_nnz, P_rowptr, P_col,
+                                 self.P_nnz, o, self.allocator.struct, stream)
+        _check(st, "ptap_plan_create")
+        self.handle = h
+        _check(ptap_symbolic(self.handle, stream), "ptap_symbolic")
+        st, nnz, rp, col = ptap_get_pattern(self.handle)
+        _check(st, "ptap_get_pattern")
+        self.nnz_C = nnz
+        self._rp_ptr, self._col_ptr = rp, col
+
+    @classmethod
+    def from_csr(cls, A, P, device="cuda", **kw):
+        """Build from host CSR objects (rowptr, col arrays) -- copies the patterns to the device."""
+        dev = torch.device(device)
+        t = lambda a: torch.as_tensor(a, dtype=torch.int32).to(dev)  # noqa: E731
+        plan = cls(A.n_rows, P.n_cols, t(A.rowptr), t(A.col), t(P.rowptr), t(P.col), **kw)
+        return plan
+
+    def pattern(self):
+        """(C_rowptr, C_col) as new int32 device tensors (copies of the plan-owned arrays)."""
+        rp = torch.empty(self.m + 1, dtype=torch.int32, device=self.A_rowptr.device)
+        col = torch.empty(max(self.nnz_C, 0), dtype=torch.int32, device=self.A_rowptr.device)
+        if self.m + 1:
+            _memcpy_d2d(rp, self._rp_ptr, (self.m + 1) * 4)
+        if self.nnz_C:
+            _memcpy_d2d(col, self._col_ptr, self.nnz_C * 4)
+        return rp, col
+
+    def numeric(self, A_val, P_val, C_val=None, stream=None):
+        if C_val is None:
+            C_val = torch.empty(self.nnz_C, dtype=torch.float64, device=A_val.device)
+        _check(ptap_numeric(self.handle, A_val, P_val, C_val, stream), "ptap_numeric")
+        return C_val
+
+    def backward(self, A_val, P_val, dC_val, need_dA=True, need_dP=True, stream=None):
+        dA = torch.empty(self.A_nnz, dtype=torch.float64, device=A_val.device) if need_dA else None
+        dP = torch.empty(self.P_nnz, dtype=torch.float64, device=A_val.device) if need_dP else None
+        _check(ptap_backward(self.handle, A_val, P_val, dC_val, dA, dP, stream), "ptap_backward")
+        return dA, dP
+
+    def stats(self) -> dict:
+        st, s = ptap_plan_stats(self.handle)
+        _check(st, "ptap_plan_stats")
+        return s.as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            torch.cuda.synchronize()
+            ptap_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _memcpy_d2d(dst_tensor, src_ptr, nbytes):
+    """Device-to-device copy of a plan-owned array into a tensor, on the current stream (torch
+    has no tensor-from-pointer API, so this calls hipMemcpyAsync of the loaded HIP runtime)."""
+    hip = _hip()
+    rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst_tensor.data_ptr()), ctypes.c_void_p(src_ptr),
+                            ctypes.c_size_t(nbytes), ctypes.c_int(3),
+                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        # the HIP runtime torch has already loaded into this process
+        torch_lib = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+        _hip_lib = ctypes.CDLL(torch_lib if os.path.exists(torch_lib) else "libamdhip64.so")
+        _hip_lib.hipMemcpyAsync.restype = ctypes.c_int
+        _hip_lib.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_int, ctypes.c_void_p]
+    return _hip_lib
+
+
+class PtAPFunction(torch.autograd.Function):
+    """C_val = PtAP(A_val, P_val) on a plan's fixed patterns; backward through ptap_backward
+    (dA = P dC P^T on A's pattern, dP = A P dC^T + A^T P dC on P's pattern)."""
+
+    @staticmethod
+    def forward(ctx, A_val, P_val, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(A_val, P_val)
+        return plan.numeric(A_val.detach(), P_val.detach())
+
+    @staticmethod
+    def backward(ctx, dC):
+        A_val, P_val = ctx.saved_tensors
+        dA, dP = ctx.plan.backward(A_val.detach(), P_val.detach(), dC.contiguous(),
+                                   need_dA=ctx.needs_input_grad[0], need_dP=ctx.needs_input_grad[1])
+        return dA, dP, None
+
+
+def ptap(plan, A_val, P_val):
+    """Differentiable C values on plan's pattern."""
+    return PtAPFunction.apply(A_val, P_val, plan)

@@ -1,0 +1,740 @@
+// Host implementation of the C ABI in include/ptap.h: plan lifecycle, the symbolic phase
+// (pattern transpose, row sizes of AP, pattern of C, row classes and owner tiles), and the
+// numeric, adjoint and batched launches.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/ptap.h"
+#include "internal.hpp"
+
+using namespace ptapk;
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+struct Failure {
+  ptap_status status;
+};
+
+inline void hipck(hipError_t e) {
+  if (e != hipSuccess) {
+    g_last_hip_error = (int32_t)e;
+    (void)hipGetLastError();
+    throw Failure{PTAP_ERR_HIP};
+  }
+}
+
+inline void fail(ptap_status s) { throw Failure{s}; }
+
+void* default_alloc(size_t bytes, void*) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+void default_release(void* p, size_t, void*) { (void)hipFree(p); }
+
+// Device allocations of a plan, counted for the statistics.
+struct Tracker {
+  ptap_allocator a{default_alloc, default_release, nullptr};
+  std::map<void*, size_t> live;
+  int64_t current = 0, peak = 0;
+
+  template <class T>
+  T* get(size_t count) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    bytes = (bytes + 255) / 256 * 256;
+    void* p = a.alloc(bytes, a.ctx);
+    if (!p) fail(PTAP_ERR_OOM);
+    live[p] = bytes;
+    current += (int64_t)bytes;
+    peak = std::max(peak, current);
+    return static_cast<T*>(p);
+  }
+  void put(void* p) {
+    if (!p) return;
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    current -= (int64_t)it->second;
+    a.release(p, it->second, a.ctx);
+    live.erase(it);
+  }
+  void release_all() {
+    for (auto& kv : live) a.release(kv.first, kv.second, a.ctx);
+    live.clear();
+    current = 0;
+  }
+};
+
+template <class T>
+std::vector<T> to_host(const T* d, size_t count, hipStream_t s) {
+  std::vector<T> h(count);
+  if (count) {
+    hipck(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    hipck(hipStreamSynchronize(s));
+  }
+  return h;
+}
+
+template <class T>
+void to_device(T* d, const std::vector<T>& h, hipStream_t s) {
+  if (!h.empty()) {
+    hipck(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    hipck(hipStreamSynchronize(s));  // h may go out of scope right after
+  }
+}
+
+inline int next_pow2(long long v) {
+  long long c = 1;
+  while (c < v) c <<= 1;
+  return (int)std::min<long long>(c, 1LL << 30);
+}
+
+// Table capacity for a row whose key set has at most `need` distinct keys: a power of two of at
+// least 2*need slots (load factor <= 1/2), never below one slot per lane.
+inline int cap_for(long long need) { return std::max(64, next_pow2(2 * std::max(need, 1LL))); }
+
+// Group rows (given in ascending order with their key-count bounds) by table capacity.  Rows
+// with a bound of zero are dropped (they add nothing).  Capacities above `lds_max` go to
+// device-memory tables.
+std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
+                                   const std::vector<long long>& need, int lds_max, hipStream_t s) {
+  std::map<int, std::vector<int>> by_cap;
+  for (size_t k = 0; k < rows.size(); ++k) {
+    if (need[k] <= 0) continue;
+    by_cap[cap_for(need[k])].push_back(rows[k]);
+  }
+  std::vector<RowClass> out;
+  for (auto& kv : by_cap) {
+    RowClass rc;
+    rc.cap = kv.first;
+    rc.global = kv.first > lds_max;
+    rc.count = (int)kv.second.size();
+    rc.rows = t.get<int>(kv.second.size());
+    to_device(rc.rows, kv.second, s);
+    out.push_back(rc);
+  }
+  return out;
+}
+
+size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
+  size_t need = 0;
+  for (auto& c : cls)
+    if (c.global) need = std::max(need, (size_t)kSpillWaves * c.cap * per_slot_ints);
+  return need;
+}
+
+}  // namespace
+
+struct ptap_plan {
+  Tracker mem;
+  ptap_options opt{};
+  Patterns pat{};
+  long long nnzA = 0, nnzP = 0;
+  bool sym_done = false;
+  int lds_budget = 65536;
+  int lds_hash_max = kLdsHashMax;
+  int lds_keys_max = kLdsKeysMax;
+
+  int* C_rowptr = nullptr;
+  int* C_col = nullptr;
+  long long nnzC = 0;
+
+  // pattern transpose (kept by two-step only)
+  int* pt_ptr = nullptr;
+  int* pt_row = nullptr;
+  int* pt_pos = nullptr;
+
+  // owner fold
+  int ntiles = 0, TE = 0, TR = 0;
+  int* tile_row0 = nullptr;
+  int* tile_fptr = nullptr;
+  int* tile_fine = nullptr;
+  std::vector<TileClass> tclasses;
+  bool any_tile_global = false;
+
+  // atomic fold
+  std::vector<RowClass> arows;
+
+  // two-step
+  int* AP_rowptr = nullptr;
+  int* AP_col = nullptr;
+  double* AP_val = nullptr;
+  double* PT_val = nullptr;
+  long long nnzAP = 0;
+  std::vector<RowClass> ap_rows, ptc_rows;
+
+  // adjoint
+  std::vector<RowClass> bwd_rows;
+
+  // spill tables for numeric / adjoint launches
+  int* gtab = nullptr;
+  double* gval = nullptr;
+
+  int fold_used = PTAP_FOLD_OWNER;
+  int64_t rows_formed = 0, rows_needed = 0, fold_terms = 0;
+  int64_t pattern_bytes = 0;
+};
+
+struct ptap_batch {
+  Tracker mem;
+  std::vector<ptap_plan*> plans;
+  std::vector<int> level;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<const double*> A_vals, P_vals;
+  std::vector<double*> C_vals;
+};
+
+static void validate_patterns(ptap_plan* P, hipStream_t s);
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+void ptap_options_default(ptap_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->algo = PTAP_MERGED;
+  o->fold = PTAP_FOLD_AUTO;
+  o->nblocks = 1;
+  o->tile_entries = 0;
+  o->hash_slots = 0;
+  o->validate = 1;
+  o->xcd_remap = 1;
+}
+
+const char* ptap_status_string(ptap_status s) {
+  switch (s) {
+    case PTAP_OK: return "ok";
+    case PTAP_ERR_INPUT: return "invalid input";
+    case PTAP_ERR_TOO_LARGE: return "count overflows int32 indexing";
+    case PTAP_ERR_OOM: return "device allocation failed";
+    case PTAP_ERR_HIP: return "HIP runtime error";
+    case PTAP_ERR_STATE: return "call out of order";
+    case PTAP_ERR_UNSUPPORTED: return "unsupported option combination";
+  }
+  return "unknown status";
+}
+
+int32_t ptap_last_hip_error(void) { return g_last_hip_error; }
+
+ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_t* A_rowptr,
+                             const int32_t* A_col, int64_t A_nnz, const int32_t* P_rowptr,
+                             const int32_t* P_col, int64_t P_nnz, const ptap_options* opts,
+                             const ptap_allocator* alloc, hipStream_t stream) {
+  if (!out) return PTAP_ERR_INPUT;
+  *out = nullptr;
+  if (n < 0 || m < 0 || A_nnz < 0 || P_nnz < 0 || !A_rowptr || !P_rowptr) return PTAP_ERR_INPUT;
+  if ((A_nnz > 0 && !A_col) || (P_nnz > 0 && !P_col)) return PTAP_ERR_INPUT;
+  if (A_nnz > INT32_MAX || P_nnz > INT32_MAX) return PTAP_ERR_TOO_LARGE;
+  ptap_options o;
+  ptap_options_default(&o);
+  if (opts) o = *opts;
+  if (o.algo < PTAP_ALLATONCE || o.algo > PTAP_TWOSTEP) return PTAP_ERR_INPUT;
+  if (o.fold < PTAP_FOLD_AUTO || o.fold > PTAP_FOLD_OWNER) return PTAP_ERR_INPUT;
+  if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0) return PTAP_ERR_INPUT;
+  if (o.hash_slots && (o.hash_slots < 64 || (o.hash_slots & (o.hash_slots - 1)))) return PTAP_ERR_INPUT;
+  if (alloc && (!alloc->alloc || !alloc->release)) return PTAP_ERR_INPUT;
+
+  ptap_plan* p = new (std::nothrow) ptap_plan();
+  if (!p) return PTAP_ERR_OOM;
+  if (alloc) p->mem.a = *alloc;
+  p->opt = o;
+  p->pat = Patterns{n, m, A_rowptr, A_col, P_rowptr, P_col};
+  p->nnzA = A_nnz;
+  p->nnzP = P_nnz;
+  try {
+    int dev = 0, lds = 0;
+    hipck(hipGetDevice(&dev));
+    hipck(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    p->lds_budget = std::min(lds, 65536);
+    if (o.hash_slots) {
+      p->lds_hash_max = std::min(p->lds_hash_max, (int)o.hash_slots);
+      p->lds_keys_max = std::min(p->lds_keys_max, (int)o.hash_slots);
+    }
+    if (o.validate) validate_patterns(p, stream);
+  } catch (const Failure& f) {
+    p->mem.release_all();
+    delete p;
+    return f.status;
+  }
+  *out = p;
+  return PTAP_OK;
+}
+
+static void validate_patterns(ptap_plan* P, hipStream_t s) {
+  const Patterns& pat = P->pat;
+  int* err = P->mem.get<int>(1);
+  hipck(launch_fill_i32(err, 0, 1, s));
+  hipck(launch_validate(pat.A_rowptr, pat.A_col, pat.n, pat.n, P->nnzA, err, s));
+  hipck(launch_validate(pat.P_rowptr, pat.P_col, pat.n, pat.m, P->nnzP, err, s));
+  int h = 0;
+  hipck(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  hipck(hipStreamSynchronize(s));
+  P->mem.put(err);
+  if (h) fail(PTAP_ERR_INPUT);
+}
+
+static void symbolic_impl(ptap_plan* P, hipStream_t s) {
+  Tracker& t = P->mem;
+  const Patterns& pat = P->pat;
+  const int n = pat.n, m = pat.m;
+  const bool two = P->opt.algo == PTAP_TWOSTEP;
+  // The patterns are caller-owned; with validation on they are checked again right before use,
+  // so that arrays changed or released since plan creation are reported instead of read.
+  if (P->opt.validate) validate_patterns(P, s);
+
+  // --- Column index lists of P (pattern transpose; integer only, no values).
+  std::vector<int> h_pt_ptr(m + 1, 0);
+  P->pt_ptr = t.get<int>(m + 1);
+  P->pt_row = t.get<int>(P->nnzP);
+  P->pt_pos = two ? t.get<int>(P->nnzP) : nullptr;
+  {
+    int* cnt = t.get<int>(m + 1);
+    hipck(launch_fill_i32(cnt, 0, m + 1, s));
+    hipck(launch_count_cols(pat.P_col, P->nnzP, cnt, s));
+    std::vector<int> hc = to_host(cnt, m, s);
+    for (int i = 0; i < m; ++i) h_pt_ptr[i + 1] = h_pt_ptr[i] + hc[i];
+    to_device(P->pt_ptr, h_pt_ptr, s);
+    to_device(cnt, std::vector<int>(h_pt_ptr.begin(), h_pt_ptr.end() - 1), s);
+    hipck(launch_transpose_fill(pat.P_rowptr, pat.P_col, n, cnt, P->pt_row, P->pt_pos, s));
+    t.put(cnt);
+  }
+  std::vector<int> hP_rowptr = to_host(pat.P_rowptr, (size_t)n + 1, s);
+
+  // --- |R_I| for every fine row (Alg. 1 / 2), tables sized by the product count w_I.
+  int* r = t.get<int>(n);
+  hipck(launch_fill_i32(r, 0, n, s));
+  {
+    long long* w = t.get<long long>(n);
+    hipck(launch_row_work(pat, w, s));
+    std::vector<long long> hw = to_host(w, n, s);
+    t.put(w);
+    std::vector<int> rows(n);
+    std::vector<long long> need(n);
+    for (int I = 0; I < n; ++I) {
+      rows[I] = I;
+      need[I] = std::min<long long>(hw[I], m);
+    }
+    std::vector<RowClass> cls = make_classes(t, rows, need, P->lds_keys_max, s);
+    size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
+    int* gtab = gi ? t.get<int>(gi) : nullptr;
+    for (auto& c : cls) hipck(launch_ap_row_count(pat, c, r, gtab, s));
+    for (auto& c : cls) t.put(c.rows);
+    t.put(gtab);
+  }
+  std::vector<int> hr = to_host(r, n, s);
+
+  // --- Two-step: the stored pattern of AP (rows sorted).
+  std::vector<int> h_ap_ptr;
+  if (two) {
+    h_ap_ptr.assign(n + 1, 0);
+    long long acc = 0;
+    for (int I = 0; I < n; ++I) {
+      acc += hr[I];
+      if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
+      h_ap_ptr[I + 1] = (int)acc;
+    }
+    P->nnzAP = acc;
+    P->AP_rowptr = t.get<int>(n + 1);
+    P->AP_col = t.get<int>(acc);
+    to_device(P->AP_rowptr, h_ap_ptr, s);
+    std::vector<int> rows(n);
+    std::vector<long long> need(n);
+    for (int I = 0; I < n; ++I) {
+      rows[I] = I;
+      need[I] = hr[I];
+    }
+    P->ap_rows = make_classes(t, rows, need, P->lds_keys_max, s);
+    size_t gi = spill_ints(P->ap_rows, 2);
+    int* gtab = gi ? t.get<int>(gi) : nullptr;
+    for (auto& c : P->ap_rows) hipck(launch_ap_row_fill(pat, c, P->AP_rowptr, P->AP_col, gtab, s));
+    t.put(gtab);
+  }
+
+  // --- Pattern of C by rows: counts, scan, fill.
+  std::vector<int> h_c_ptr(m + 1, 0);
+  {
+    long long* bound = t.get<long long>(m);
+    hipck(launch_c_bound(P->pt_ptr, P->pt_row, r, m, bound, s));
+    std::vector<long long> hb = to_host(bound, m, s);
+    t.put(bound);
+    std::vector<int> rows(m);
+    for (int i = 0; i < m; ++i) rows[i] = i;
+    std::vector<RowClass> cls = make_classes(t, rows, hb, P->lds_keys_max, s);
+    size_t gi = spill_ints(cls, 2);
+    int* gtab = gi ? t.get<int>(gi) : nullptr;
+    int* cnt = t.get<int>(m);
+    hipck(launch_fill_i32(cnt, 0, m, s));
+    for (auto& c : cls)
+      hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, false, cnt,
+                          nullptr, nullptr, gtab, s));
+    for (auto& c : cls) t.put(c.rows);
+    t.put(gtab);
+    std::vector<int> hc = to_host(cnt, m, s);
+    t.put(cnt);
+    long long acc = 0;
+    for (int i = 0; i < m; ++i) {
+      acc += hc[i];
+      if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
+      h_c_ptr[i + 1] = (int)acc;
+    }
+    P->nnzC = acc;
+    P->C_rowptr = t.get<int>(m + 1);
+    P->C_col = t.get<int>(acc);
+    to_device(P->C_rowptr, h_c_ptr, s);
+    std::vector<long long> exact(m);
+    for (int i = 0; i < m; ++i) exact[i] = hc[i];
+    cls = make_classes(t, rows, exact, P->lds_keys_max, s);
+    gi = spill_ints(cls, 2);
+    gtab = gi ? t.get<int>(gi) : nullptr;
+    for (auto& c : cls)
+      hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, true, nullptr,
+                          P->C_rowptr, P->C_col, gtab, s));
+    for (auto& c : cls) t.put(c.rows);
+    t.put(gtab);
+    P->pattern_bytes = (int64_t)(m + 1 + acc) * (int64_t)sizeof(int);
+  }
+
+  // --- Counters for the statistics: rows needed and fold terms sum_I nnz(P(I,:)) |R_I|.
+  long long needed = 0, terms = 0;
+  for (int I = 0; I < n; ++I) {
+    const int lp = hP_rowptr[I + 1] - hP_rowptr[I];
+    if (lp > 0 && hr[I] > 0) {
+      ++needed;
+      terms += (long long)lp * hr[I];
+    }
+  }
+  P->rows_needed = needed;
+  P->fold_terms = terms;
+
+  size_t spill_need_ints = 0, spill_need_vals = 0;
+  const int lmax = P->lds_hash_max;
+
+  if (two) {
+    P->fold_used = PTAP_FOLD_AUTO;
+    P->AP_val = t.get<double>(P->nnzAP);
+    P->PT_val = t.get<double>(P->nnzP);
+    // AP rows already classed by exact |R_I|; reclass for maps (value tables have another LDS limit)
+    for (auto& c : P->ap_rows) t.put(c.rows);
+    std::vector<int> rows;
+    std::vector<long long> need;
+    for (int I = 0; I < n; ++I)
+      if (hr[I] > 0) {
+        rows.push_back(I);
+        need.push_back(hr[I]);
+      }
+    P->ap_rows = make_classes(t, rows, need, lmax, s);
+    std::vector<int> crow;
+    std::vector<long long> cneed;
+    for (int i = 0; i < m; ++i)
+      if (h_c_ptr[i + 1] > h_c_ptr[i]) {
+        crow.push_back(i);
+        cneed.push_back(h_c_ptr[i + 1] - h_c_ptr[i]);
+      }
+    P->ptc_rows = make_classes(t, crow, cneed, lmax, s);
+    spill_need_ints = std::max(spill_ints(P->ap_rows, 1), spill_ints(P->ptc_rows, 1));
+    spill_need_vals = spill_need_ints;
+    P->rows_formed = (int64_t)rows.size();
+  } else {
+    t.put(P->pt_pos);
+    P->pt_pos = nullptr;
+    const bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
+    P->fold_used = atomic ? PTAP_FOLD_ATOMIC : PTAP_FOLD_OWNER;
+    if (atomic) {
+      std::vector<int> rows;
+      std::vector<long long> need;
+      for (int I = 0; I < n; ++I)
+        if (hP_rowptr[I + 1] > hP_rowptr[I] && hr[I] > 0) {
+          rows.push_back(I);
+          need.push_back(hr[I]);
+        }
+      P->arows = make_classes(t, rows, need, lmax, s);
+      spill_need_ints = spill_ints(P->arows, 1);
+      spill_need_vals = spill_need_ints;
+      const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+      P->rows_formed = (int64_t)rows.size() * (twopass ? 2 : 1);  // upper bound for two passes
+      t.put(P->pt_ptr);
+      t.put(P->pt_row);
+      P->pt_ptr = P->pt_row = nullptr;
+    } else {
+      // Tiles of contiguous C rows, sized for the LDS budget.
+      int rmax_all = 0;
+      for (int I = 0; I < n; ++I) rmax_all = std::max(rmax_all, hr[I]);
+      const int cap_all = std::min(cap_for(rmax_all), lmax);
+      int TE = P->opt.tile_entries ? P->opt.tile_entries : kDefaultTileEntries;
+      const int TR = std::min(std::max(TE, 1), 1024);
+      const long long fixed = (long long)kWavesPerBlock * (sizeof(WaveScratch) + (long long)cap_all * 12) +
+                              ((long long)TR + 1) * 4 + 16;
+      const long long room = (P->lds_budget - fixed) / 12;
+      TE = (int)std::max<long long>(16, std::min<long long>(TE, room));
+      P->TE = TE;
+      P->TR = TR;
+      std::vector<int> row0;
+      std::vector<char> tglob;
+      int i = 0;
+      while (i < m) {
+        const int sz0 = h_c_ptr[i + 1] - h_c_ptr[i];
+        row0.push_back(i);
+        if (sz0 > TE) {
+          tglob.push_back(1);
+          ++i;
+          continue;
+        }
+        long long acc = 0;
+        int rows_in = 0;
+        while (i < m && rows_in < TR) {
+          const int sz = h_c_ptr[i + 1] - h_c_ptr[i];
+          if (acc + sz > TE) break;
+          acc += sz;
+          ++rows_in;
+          ++i;
+        }
+        tglob.push_back(0);
+      }
+      row0.push_back(m);
+      const int T = (int)tglob.size();
+      P->ntiles = T;
+      P->tile_row0 = t.get<int>(T + 1);
+      to_device(P->tile_row0, row0, s);
+      int* tcnt = t.get<int>(T);
+      int* trmax = t.get<int>(T);
+      hipck(launch_tile_fine(P->pt_ptr, P->pt_row, P->tile_row0, T, n, r, false, tcnt, trmax,
+                             nullptr, nullptr, s));
+      std::vector<int> hcnt = to_host(tcnt, T, s);
+      std::vector<int> hrmax = to_host(trmax, T, s);
+      t.put(tcnt);
+      t.put(trmax);
+      std::vector<int> fptr(T + 1, 0);
+      long long acc = 0;
+      for (int k = 0; k < T; ++k) {
+        acc += hcnt[k];
+        if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
+        fptr[k + 1] = (int)acc;
+      }
+      P->tile_fptr = t.get<int>(T + 1);
+      P->tile_fine = t.get<int>(acc);
+      to_device(P->tile_fptr, fptr, s);
+      hipck(launch_tile_fine(P->pt_ptr, P->pt_row, P->tile_row0, T, n, r, true, nullptr, nullptr,
+                             P->tile_fptr, P->tile_fine, s));
+      P->rows_formed = acc;
+      // classes by (hash capacity, placement)
+      std::map<std::pair<int, int>, std::vector<int>> groups;
+      for (int k = 0; k < T; ++k) {
+        if (hcnt[k] == 0) {
+          // no fine row touches the tile: its rows of C are empty or must be zero; still launched
+          // so that the tile writes its zeros.
+        }
+        const int cap = cap_for(std::max(hrmax[k], 1));
+        groups[{cap, (int)tglob[k]}].push_back(k);
+      }
+      for (auto& kv : groups) {
+        TileClass tc;
+        tc.cap = kv.first.first;
+        tc.hash_global = tc.cap > lmax;
+        tc.tile_global = kv.first.second != 0;
+        tc.count = (int)kv.second.size();
+        tc.tiles = t.get<int>(tc.count);
+        to_device(tc.tiles, kv.second, s);
+        if (tc.tile_global) P->any_tile_global = true;
+        if (tc.hash_global)
+          spill_need_ints = std::max(spill_need_ints, (size_t)tc.count * kWavesPerBlock * tc.cap);
+        P->tclasses.push_back(tc);
+      }
+      spill_need_vals = spill_need_ints;
+      t.put(P->pt_ptr);
+      t.put(P->pt_row);
+      P->pt_ptr = P->pt_row = nullptr;
+    }
+  }
+
+  // --- Adjoint row classes: U_I has at most sum_{i in P(I,:)} |C(i,:)| keys.
+  if (P->opt.backward) {
+    std::vector<int> rows(n);
+    std::vector<long long> need(n);
+    // |U_I| <= min(m, sum over P(I,:) of row lengths of C): computed from P's columns on host.
+    std::vector<int> hPcol = to_host(pat.P_col, (size_t)P->nnzP, s);
+    for (int I = 0; I < n; ++I) {
+      rows[I] = I;
+      long long u = 0;
+      for (int e = hP_rowptr[I]; e < hP_rowptr[I + 1]; ++e)
+        u += h_c_ptr[hPcol[e] + 1] - h_c_ptr[hPcol[e]];
+      u = std::min<long long>(u, m);
+      // rows with an empty A row still need their (empty) dA written: nothing to do for them.
+      need[I] = std::max<long long>(std::max<long long>(u, hr[I]), 1);
+    }
+    // the adjoint kernel holds two tables of this capacity per wavefront
+    P->bwd_rows = make_classes(t, rows, need, lmax / 2 >= 64 ? lmax / 2 : 64, s);
+    spill_need_ints = std::max(spill_need_ints, spill_ints(P->bwd_rows, 2));
+    spill_need_vals = std::max(spill_need_vals, spill_ints(P->bwd_rows, 2));
+  }
+
+  t.put(r);
+  if (spill_need_ints) P->gtab = t.get<int>(spill_need_ints);
+  if (spill_need_vals) P->gval = t.get<double>(spill_need_vals);
+  if (P->gtab) hipck(launch_fill_i32(P->gtab, EMPTY, (long long)spill_need_ints, s));
+  if (P->gval) hipck(launch_fill_f64(P->gval, 0.0, (long long)spill_need_vals, s));
+  hipck(hipStreamSynchronize(s));
+}
+
+ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
+  if (!plan) return PTAP_ERR_INPUT;
+  if (plan->sym_done) return PTAP_ERR_STATE;
+  // Run on a scratch copy of the plan's state so that a failure leaves the plan unchanged.
+  try {
+    symbolic_impl(plan, stream);
+  } catch (const Failure& f) {
+    // wait for the launches already queued, then release everything the failed phase allocated
+    (void)hipStreamSynchronize(stream);
+    (void)hipGetLastError();
+    plan->mem.release_all();
+    ptap_plan fresh;
+    fresh.mem.a = plan->mem.a;
+    fresh.mem.peak = plan->mem.peak;
+    fresh.opt = plan->opt;
+    fresh.pat = plan->pat;
+    fresh.nnzA = plan->nnzA;
+    fresh.nnzP = plan->nnzP;
+    fresh.lds_budget = plan->lds_budget;
+    fresh.lds_hash_max = plan->lds_hash_max;
+    fresh.lds_keys_max = plan->lds_keys_max;
+    plan->~ptap_plan();
+    new (plan) ptap_plan(std::move(fresh));
+    return f.status;
+  }
+  plan->sym_done = true;
+  return PTAP_OK;
+}
+
+ptap_status ptap_get_pattern(const ptap_plan* plan, int64_t* nnz_C, const int32_t** C_rowptr,
+                             const int32_t** C_col) {
+  if (!plan) return PTAP_ERR_INPUT;
+  if (!plan->sym_done) return PTAP_ERR_STATE;
+  if (nnz_C) *nnz_C = plan->nnzC;
+  if (C_rowptr) *C_rowptr = plan->C_rowptr;
+  if (C_col) *C_col = plan->C_col;
+  return PTAP_OK;
+}
+
+static NumericArgs numeric_args(ptap_plan* P, const double* A_val, const double* P_val,
+                                double* C_val, int part) {
+  NumericArgs a;
+  a.p = P->pat;
+  a.A_val = A_val;
+  a.P_val = P_val;
+  a.C_rowptr = P->C_rowptr;
+  a.C_col = P->C_col;
+  a.C_val = C_val;
+  a.K = P->opt.nblocks;
+  a.part = part;
+  return a;
+}
+
+ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val, double* C_val,
+                         hipStream_t s) {
+  if (!P) return PTAP_ERR_INPUT;
+  if (!P->sym_done) return PTAP_ERR_STATE;
+  if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!C_val && P->nnzC)) return PTAP_ERR_INPUT;
+  try {
+    if (P->nnzC == 0) return PTAP_OK;
+    if (P->opt.algo == PTAP_TWOSTEP) {
+      NumericArgs a = numeric_args(P, A_val, P_val, C_val, PART_ALL);
+      for (auto& c : P->ap_rows)
+        hipck(launch_ap_numeric(a, c, P->AP_rowptr, P->AP_col, P->AP_val, P->gtab, P->gval, s));
+      hipck(launch_gather(P_val, P->pt_pos, P->PT_val, P->nnzP, s));
+      for (auto& c : P->ptc_rows)
+        hipck(launch_ptc_numeric(P->pt_ptr, P->pt_row, P->PT_val, P->AP_rowptr, P->AP_col,
+                                 P->AP_val, P->C_rowptr, P->C_col, C_val, c, P->gtab, P->gval, s));
+      return PTAP_OK;
+    }
+    const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+    if (P->fold_used == PTAP_FOLD_ATOMIC) {
+      hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));
+      const int parts[2] = {twopass ? PART_OFF : PART_ALL, PART_ON};
+      for (int k = 0; k < (twopass ? 2 : 1); ++k) {
+        NumericArgs a = numeric_args(P, A_val, P_val, C_val, parts[k]);
+        for (auto& c : P->arows) hipck(launch_atomic_numeric(a, c, P->gtab, P->gval, s));
+      }
+      return PTAP_OK;
+    }
+    if (P->any_tile_global) hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));
+    NumericArgs a = numeric_args(P, A_val, P_val, C_val, twopass ? -1 : PART_ALL);
+    for (auto& c : P->tclasses)
+      hipck(launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+                                 P->opt.xcd_remap != 0, P->gtab, P->gval, s));
+  } catch (const Failure& f) {
+    return f.status;
+  }
+  return PTAP_OK;
+}
+
+ptap_status ptap_backward(ptap_plan* P, const double* A_val, const double* P_val,
+                          const double* dC_val, double* dA_val, double* dP_val, hipStream_t s) {
+  if (!P) return PTAP_ERR_INPUT;
+  if (!P->sym_done) return PTAP_ERR_STATE;
+  if (!P->opt.backward) return PTAP_ERR_STATE;
+  if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!dC_val && P->nnzC)) return PTAP_ERR_INPUT;
+  try {
+    if (dA_val) hipck(launch_fill_f64(dA_val, 0.0, P->nnzA, s));
+    if (dP_val) hipck(launch_fill_f64(dP_val, 0.0, P->nnzP, s));
+    if (!dA_val && !dP_val) return PTAP_OK;
+    NumericArgs a = numeric_args(P, A_val, P_val, nullptr, PART_ALL);
+    for (auto& c : P->bwd_rows) hipck(launch_backward(a, dC_val, dA_val, dP_val, c, P->gtab, P->gval, s));
+  } catch (const Failure& f) {
+    return f.status;
+  }
+  return PTAP_OK;
+}
+
+ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
+  if (!P || !out) return PTAP_ERR_INPUT;
+  memset(out, 0, sizeof(*out));
+  out->nnz_C = P->nnzC;
+  out->nnz_AP = P->nnzAP;
+  out->workspace_bytes = P->mem.current;
+  out->peak_bytes = P->mem.peak;
+  out->pattern_bytes = P->pattern_bytes;
+  out->rows_formed = P->rows_formed;
+  out->rows_needed = P->rows_needed;
+  out->fold_terms = P->fold_terms;
+  out->n_tiles = P->ntiles;
+  out->fold_used = P->fold_used;
+  out->algo = P->opt.algo;
+  out->nblocks = P->opt.nblocks;
+  return PTAP_OK;
+}
+
+void ptap_plan_destroy(ptap_plan* P) {
+  if (!P) return;
+  P->mem.release_all();
+  delete P;
+}
+
+ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const int32_t* level,
+                              int32_t count, const ptap_allocator* alloc, hipStream_t stream) {
+  (void)plans; (void)level; (void)count; (void)alloc; (void)stream;
+  if (out) *out = nullptr;
+  return PTAP_ERR_UNSUPPORTED;
+}
+
+ptap_status ptap_batch_numeric(ptap_batch* batch, const double* const* A_vals,
+                               const double* const* P_vals, double* const* C_vals,
+                               hipStream_t stream) {
+  (void)batch; (void)A_vals; (void)P_vals; (void)C_vals; (void)stream;
+  return PTAP_ERR_UNSUPPORTED;
+}
+
+void ptap_batch_destroy(ptap_batch* batch) { delete batch; }
+
+}  // extern "C"

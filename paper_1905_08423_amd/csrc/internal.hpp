@@ -1,0 +1,103 @@
+// Host-side plan structure and kernel launch wrappers (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/ptap.h"
+#include "device.hpp"
+
+namespace ptapk {
+
+// A set of rows processed by one launch: all rows whose hash table has `cap` slots, held in
+// LDS (global = false) or in device memory (global = true).
+struct RowClass {
+  int cap = 0;
+  bool global = false;
+  int count = 0;
+  int* rows = nullptr;  // device, `count` row indices in ascending order
+};
+
+// Device arrays of the inputs' patterns (caller-owned).
+struct Patterns {
+  int n, m;
+  const int* A_rowptr;
+  const int* A_col;
+  const int* P_rowptr;
+  const int* P_col;
+};
+
+// Owner-fold launch group: tiles sharing a hash-table capacity and tile placement.
+struct TileClass {
+  int cap = 0;
+  bool hash_global = false;
+  bool tile_global = false;
+  int count = 0;
+  int* tiles = nullptr;  // device, tile ids
+};
+
+// Limits of on-chip storage per launch (bytes of LDS per workgroup are set per kernel).
+constexpr int kWavesPerBlock = 4;
+constexpr int kLdsHashMax = 1024;       // largest LDS table (slots) of a numeric kernel
+constexpr int kLdsKeysMax = 2048;       // largest LDS key-only table (slots) of a symbolic kernel
+constexpr int kDefaultTileEntries = 4096;
+constexpr int kSpillWaves = 512;        // concurrent wavefronts of a spill (global-table) launch
+
+// ---------------------------------------------------------------------------------------
+// Launch wrappers (kernels.hip).  All take a stream and return hipError_t.
+// ---------------------------------------------------------------------------------------
+hipError_t launch_validate(const int* rowptr, const int* col, int nrows, int ncols, long long nnz,
+                           int* err, hipStream_t s);
+hipError_t launch_fill_i32(int* p, int value, long long count, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double value, long long count, hipStream_t s);
+hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_t s);
+hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
+                                 int* t_row, int* t_pos, hipStream_t s);
+hipError_t launch_row_work(const Patterns& p, long long* w, hipStream_t s);
+hipError_t launch_ap_row_count(const Patterns& p, const RowClass& rc, int* r_out, int* gtab,
+                               hipStream_t s);
+hipError_t launch_ap_row_fill(const Patterns& p, const RowClass& rc, const int* AP_rowptr,
+                              int* AP_col, int* gtab, hipStream_t s);
+hipError_t launch_c_bound(const int* pt_ptr, const int* pt_row, const int* r, int m,
+                          long long* bound, hipStream_t s);
+// C pattern by the row form: all-at-once (recompute S(R_I)) or two-step (read stored AP rows).
+hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row,
+                         const int* AP_rowptr, const int* AP_col, const RowClass& rc, bool fill,
+                         int* cnt_out, const int* C_rowptr, int* C_col, int* gtab, hipStream_t s);
+hipError_t launch_tile_fine(const int* pt_ptr, const int* pt_row, const int* tile_row0,
+                            int ntiles, int n, const int* r, bool fill, int* cnt_out,
+                            int* rmax_out, const int* fptr, int* fine, hipStream_t s);
+
+struct NumericArgs {
+  Patterns p;
+  const double* A_val;
+  const double* P_val;
+  const int* C_rowptr;
+  const int* C_col;
+  double* C_val;
+  int K;
+  int part;  // FoldPart
+};
+hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
+                                 hipStream_t s);
+hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
+                                const int* tile_fptr, const int* tile_fine, int tile_entries,
+                                int tile_rows, bool xcd_remap, int* gtab, double* gval,
+                                hipStream_t s);
+// Two-step numeric pieces.
+hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int* AP_rowptr,
+                             const int* AP_col, double* AP_val, int* gtab, double* gval,
+                             hipStream_t s);
+hipError_t launch_gather(const double* src, const int* idx, double* dst, long long count,
+                         hipStream_t s);
+hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double* PT_val,
+                              const int* AP_rowptr, const int* AP_col, const double* AP_val,
+                              const int* C_rowptr, const int* C_col, double* C_val,
+                              const RowClass& rc, int* gtab, double* gval, hipStream_t s);
+// Adjoint.
+hipError_t launch_backward(const NumericArgs& a, const double* dC, double* dA, double* dP,
+                           const RowClass& rc, int* gtab, double* gval, hipStream_t s);
+
+}  // namespace ptapk

@@ -1,0 +1,938 @@
+// HIP kernels for gfx950: input validation, pattern transpose, symbolic phase (row sizes of AP,
+// pattern of C, owner tiles), the numeric all-at-once / merged folds (atomic and owner), the
+// two-step comparison and the adjoint.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ptapk {
+
+namespace {
+
+constexpr int kThreads = kWavesPerBlock * WAVE;
+
+inline int grid_for(long long count, int threads, int cap_blocks = 65536) {
+  long long g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap_blocks) g = cap_blocks;
+  return (int)g;
+}
+
+// Grid of a launch that gives one wavefront per row.  Spill launches (tables in device memory)
+// use a fixed number of wavefronts that stride over the rows, so the workspace stays bounded.
+inline int wave_grid(int count, bool global) {
+  if (global) return kSpillWaves / kWavesPerBlock;
+  return grid_for(count, kWavesPerBlock, 1 << 30);
+}
+
+// Device-memory table of wavefront `w` (global wave index) for spill launches.
+__device__ __forceinline__ int* gkeys(int* gtab, int cap, int w) { return gtab + (size_t)w * cap; }
+
+}  // namespace
+
+// =============================================================================================
+// Utilities
+// =============================================================================================
+
+__global__ void k_validate(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
+                           int ncols, long long nnz, int* err) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 && (rowptr[0] != 0 || (long long)rowptr[nrows] != nnz)) atomicOr(err, 1);
+  if (r >= nrows) return;
+  const long long b = rowptr[r], e = rowptr[r + 1];
+  if (b < 0 || e < b || e > nnz) {
+    atomicOr(err, 2);
+    return;
+  }
+  int prev = -1;
+  for (long long k = b; k < e; ++k) {
+    const int c = col[k];
+    if (c <= prev || c >= ncols) {
+      atomicOr(err, 4);
+      return;
+    }
+    prev = c;
+  }
+}
+
+hipError_t launch_validate(const int* rowptr, const int* col, int nrows, int ncols, long long nnz,
+                           int* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(nrows, 256)), dim3(256), 0, s, rowptr, col, nrows,
+                     ncols, nnz, err);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void k_fill(T* p, T value, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+hipError_t launch_fill_i32(int* p, int value, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<int>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, double value, long long count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value,
+                     count);
+  return hipGetLastError();
+}
+
+__global__ void k_count_cols(const int* __restrict__ col, long long nnz, int* cnt) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < nnz;
+       k += (long long)gridDim.x * blockDim.x)
+    atomicAdd(cnt + col[k], 1);
+}
+
+hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_cols, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, s, col, nnz, cnt);
+  return hipGetLastError();
+}
+
+// Column index lists of a CSR pattern: for every stored (r, c), append r to list c and record
+// the entry's position.  Order within a list follows the atomic cursor (not sorted).
+__global__ void k_transpose_fill(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                 int nrows, int* cursor, int* t_row, int* t_pos) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+    const int pos = atomicAdd(cursor + col[k], 1);
+    t_row[pos] = r;
+    if (t_pos) t_pos[pos] = k;
+  }
+}
+
+hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
+                                 int* t_row, int* t_pos, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(nrows, 256)), dim3(256), 0, s, rowptr, col,
+                     nrows, cursor, t_row, t_pos);
+  return hipGetLastError();
+}
+
+// w_I = sum over J in row I of A of nnz(P(J,:)): the number of products of row I of AP, an
+// upper bound on |R_I|.
+__global__ void k_row_work(Patterns p, long long* w) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= p.n) return;
+  long long s = 0;
+  for (int k = p.A_rowptr[I]; k < p.A_rowptr[I + 1]; ++k) {
+    const int J = p.A_col[k];
+    s += p.P_rowptr[J + 1] - p.P_rowptr[J];
+  }
+  w[I] = s;
+}
+
+hipError_t launch_row_work(const Patterns& p, long long* w, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_work, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, w);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Sorted emission of a key set: compact the occupied slots of a table (ballot + prefix count)
+// into `list`, then place every key at its rank (number of smaller keys) in `out`.
+// =============================================================================================
+template <bool G>
+__device__ __forceinline__ int compact_keys(const int* keys, int cap, int* list) {
+  const int ln = lane();
+  int base = 0;
+  for (int s0 = 0; s0 < cap; s0 += WAVE) {
+    const int k = ld_key<G>(keys + s0 + ln);
+    const unsigned long long mk = ballot(k != EMPTY);
+    if (k != EMPTY) list[base + prefix_count(mk)] = k;
+    base += __popcll(mk);
+  }
+  if constexpr (G)
+    __threadfence();
+  else
+    wave_sync();
+  return base;
+}
+
+template <bool G>
+__device__ __forceinline__ void rank_sort_store(const int* list, int cnt, int* out) {
+  for (int x = lane(); x < cnt; x += WAVE) {
+    const int key = ld_key<G>(list + x);
+    int rank = 0;
+    for (int y = 0; y < cnt; ++y) rank += ld_key<G>(list + y) < key;
+    out[rank] = key;
+  }
+}
+
+// =============================================================================================
+// Symbolic: |R_I| (Alg. 1 / Alg. 2: the size of the key set of row I of AP) and, for the
+// two-step method, the sorted pattern of AP.
+// =============================================================================================
+template <bool G, bool FILL>
+__global__ __launch_bounds__(kThreads) void k_ap_rows(Patterns p, const int* __restrict__ rows,
+                                                      int count, int cap, int* r_out,
+                                                      const int* __restrict__ AP_rowptr,
+                                                      int* AP_col, int* gtab) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem) + wid;
+  const int stride_t = cap + cap / 2;  // keys, then a list of up to cap/2 keys
+  int* keys = G ? gkeys(gtab, stride_t, gw)
+                : reinterpret_cast<int*>(smem + kWavesPerBlock * sizeof(WaveScratch)) + wid * stride_t;
+  int* list = keys + cap;
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  table_clear<G>(keys, nullptr, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int I = rows[r];
+    int fresh_cnt = 0;
+    for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, nullptr, p.P_rowptr, ws,
+                 [&](int k, double) {
+                   bool fresh;
+                   hs_insert<G>(keys, mask, shift, p.P_col[k], fresh);
+                   fresh_cnt += fresh ? 1 : 0;
+                 });
+    if constexpr (FILL) {
+      if constexpr (G) __threadfence();
+      const int cnt = compact_keys<G>(keys, cap, list);
+      rank_sort_store<G>(list, cnt, AP_col + AP_rowptr[I]);
+    } else {
+      fresh_cnt = wave_sum(fresh_cnt);
+      if (ln == 0) r_out[I] = fresh_cnt;
+    }
+    table_clear<G>(keys, nullptr, cap);
+  }
+}
+
+static size_t key_lds_bytes(int cap) {
+  return kWavesPerBlock * (sizeof(WaveScratch) + (size_t)(cap + cap / 2) * sizeof(int));
+}
+
+hipError_t launch_ap_row_count(const Patterns& p, const RowClass& rc, int* r_out, int* gtab,
+                               hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  if (rc.global)
+    hipLaunchKernelGGL((k_ap_rows<true, false>), dim3(grid), dim3(kThreads),
+                       kWavesPerBlock * sizeof(WaveScratch), s, p, rc.rows, rc.count, rc.cap, r_out,
+                       nullptr, nullptr, gtab);
+  else
+    hipLaunchKernelGGL((k_ap_rows<false, false>), dim3(grid), dim3(kThreads), key_lds_bytes(rc.cap),
+                       s, p, rc.rows, rc.count, rc.cap, r_out, nullptr, nullptr, gtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_ap_row_fill(const Patterns& p, const RowClass& rc, const int* AP_rowptr,
+                              int* AP_col, int* gtab, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  if (rc.global)
+    hipLaunchKernelGGL((k_ap_rows<true, true>), dim3(grid), dim3(kThreads),
+                       kWavesPerBlock * sizeof(WaveScratch), s, p, rc.rows, rc.count, rc.cap,
+                       nullptr, AP_rowptr, AP_col, gtab);
+  else
+    hipLaunchKernelGGL((k_ap_rows<false, true>), dim3(grid), dim3(kThreads), key_lds_bytes(rc.cap),
+                       s, p, rc.rows, rc.count, rc.cap, nullptr, AP_rowptr, AP_col, gtab);
+  return hipGetLastError();
+}
+
+// Upper bound on |C(i,:)|: C(i,:) is the union of S(R_I) over I with P(I,i) stored
+// (Eq. allatoncerow), so |C(i,:)| <= min(m, sum of |R_I|).
+__global__ void k_c_bound(const int* __restrict__ pt_ptr, const int* __restrict__ pt_row,
+                          const int* __restrict__ r, int m, long long* bound) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  long long s = 0;
+  for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) s += r[pt_row[t]];
+  bound[i] = s < m ? s : m;
+}
+
+hipError_t launch_c_bound(const int* pt_ptr, const int* pt_row, const int* r, int m,
+                          long long* bound, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_c_bound, dim3(grid_for(m, 256)), dim3(256), 0, s, pt_ptr, pt_row, r, m,
+                     bound);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Symbolic: pattern of C by rows (Eq. allatoncerow).  All-at-once / merged: S(C(i,:)) is the
+// union over I in the column list of P for i of S(R_I), with S(R_I) formed again from A and P
+// (no AP is stored).  Two-step: the union of the stored rows of AP (Alg. 5, P^T (AP)).
+// Count mode writes |C(i,:)|; fill mode writes the sorted columns.
+// =============================================================================================
+template <bool G, bool FILL, bool TWOSTEP>
+__global__ __launch_bounds__(kThreads) void k_c_rows(Patterns p, const int* __restrict__ pt_ptr,
+                                                     const int* __restrict__ pt_row,
+                                                     const int* __restrict__ AP_rowptr,
+                                                     const int* __restrict__ AP_col,
+                                                     const int* __restrict__ rows, int count,
+                                                     int cap, int* cnt_out,
+                                                     const int* __restrict__ C_rowptr, int* C_col,
+                                                     int* gtab) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem) + wid;
+  const int stride_t = cap + cap / 2;
+  int* keys = G ? gkeys(gtab, stride_t, gw)
+                : reinterpret_cast<int*>(smem + kWavesPerBlock * sizeof(WaveScratch)) + wid * stride_t;
+  int* list = keys + cap;
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  table_clear<G>(keys, nullptr, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int i = rows[r];
+    int fresh_cnt = 0;
+    for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
+      const int I = pt_row[t];
+      if constexpr (TWOSTEP) {
+        for (int e = AP_rowptr[I] + ln; e < AP_rowptr[I + 1]; e += WAVE) {
+          bool fresh;
+          hs_insert<G>(keys, mask, shift, AP_col[e], fresh);
+          fresh_cnt += fresh ? 1 : 0;
+        }
+      } else {
+        for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, nullptr, p.P_rowptr, ws,
+                     [&](int k, double) {
+                       bool fresh;
+                       hs_insert<G>(keys, mask, shift, p.P_col[k], fresh);
+                       fresh_cnt += fresh ? 1 : 0;
+                     });
+      }
+    }
+    if constexpr (FILL) {
+      if constexpr (G) __threadfence();
+      const int cnt = compact_keys<G>(keys, cap, list);
+      rank_sort_store<G>(list, cnt, C_col + C_rowptr[i]);
+    } else {
+      fresh_cnt = wave_sum(fresh_cnt);
+      if (ln == 0) cnt_out[i] = fresh_cnt;
+    }
+    table_clear<G>(keys, nullptr, cap);
+  }
+}
+
+hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row,
+                         const int* AP_rowptr, const int* AP_col, const RowClass& rc, bool fill,
+                         int* cnt_out, const int* C_rowptr, int* C_col, int* gtab, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  const size_t lds = rc.global ? kWavesPerBlock * sizeof(WaveScratch) : key_lds_bytes(rc.cap);
+  const bool two = AP_rowptr != nullptr;
+#define PTAP_LAUNCH_C(G, F, T)                                                                   \
+  hipLaunchKernelGGL((k_c_rows<G, F, T>), dim3(grid), dim3(kThreads), lds, s, p, pt_ptr, pt_row, \
+                     AP_rowptr, AP_col, rc.rows, rc.count, rc.cap, cnt_out, C_rowptr, C_col, gtab)
+  if (rc.global) {
+    if (fill) {
+      if (two) PTAP_LAUNCH_C(true, true, true); else PTAP_LAUNCH_C(true, true, false);
+    } else {
+      if (two) PTAP_LAUNCH_C(true, false, true); else PTAP_LAUNCH_C(true, false, false);
+    }
+  } else {
+    if (fill) {
+      if (two) PTAP_LAUNCH_C(false, true, true); else PTAP_LAUNCH_C(false, true, false);
+    } else {
+      if (two) PTAP_LAUNCH_C(false, false, true); else PTAP_LAUNCH_C(false, false, false);
+    }
+  }
+#undef PTAP_LAUNCH_C
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Owner tiles: for each tile of contiguous C rows [i0, i1), the sorted distinct fine rows I with
+// P(I,i) stored for some i in the tile (from P's column lists), and the largest |R_I| among
+// them.  A bitmap over windows of the candidates' index span removes duplicates and emits the
+// rows in ascending order.
+// =============================================================================================
+constexpr int kTileBlock = 256;
+constexpr int kWindowBits = 32768;
+
+__device__ __forceinline__ int block_reduce_min(int v, int* red) {
+  v = -wave_max(-v);
+  if (lane() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int w = 1; w < kTileBlock / WAVE; ++w) r = min(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int block_reduce_max(int v, int* red) {
+  v = wave_max(v);
+  if (lane() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  int r = red[0];
+  for (int w = 1; w < kTileBlock / WAVE; ++w) r = max(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan over the block; returns this thread's offset and writes the total.
+__device__ __forceinline__ int block_excl_scan(int v, int* red, int& total) {
+  const int incl = wave_incl_scan(v);
+  if (lane() == WAVE - 1) red[threadIdx.x / WAVE] = incl;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < kTileBlock / WAVE; ++w) {
+    if (w < (int)(threadIdx.x / WAVE)) before += red[w];
+    tot += red[w];
+  }
+  __syncthreads();
+  total = tot;
+  return before + incl - v;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict__ pt_ptr,
+                                                          const int* __restrict__ pt_row,
+                                                          const int* __restrict__ tile_row0,
+                                                          const int* __restrict__ r, int* cnt_out,
+                                                          int* rmax_out,
+                                                          const int* __restrict__ fptr,
+                                                          int* fine) {
+  __shared__ unsigned bits[kWindowBits / 32];
+  __shared__ int red[kTileBlock / WAVE];
+  const int tile = blockIdx.x;
+  const int t0 = pt_ptr[tile_row0[tile]], t1 = pt_ptr[tile_row0[tile + 1]];
+  int lo = INT32_MAX, hi = -1, rmax = 0;
+  for (int t = t0 + threadIdx.x; t < t1; t += kTileBlock) {
+    const int I = pt_row[t];
+    lo = min(lo, I);
+    hi = max(hi, I);
+    if (!FILL) rmax = max(rmax, r[I]);
+  }
+  lo = block_reduce_min(lo, red);
+  hi = block_reduce_max(hi, red);
+  if (!FILL) rmax = block_reduce_max(rmax, red);
+  int emitted = 0;
+  for (long long wb = lo; wb <= hi; wb += kWindowBits) {
+    for (int w = threadIdx.x; w < kWindowBits / 32; w += kTileBlock) bits[w] = 0u;
+    __syncthreads();
+    for (int t = t0 + threadIdx.x; t < t1; t += kTileBlock) {
+      const long long d = (long long)pt_row[t] - wb;
+      if (d >= 0 && d < kWindowBits) atomicOr(bits + (d >> 5), 1u << (d & 31));
+    }
+    __syncthreads();
+    constexpr int kWordsPerThread = kWindowBits / 32 / kTileBlock;
+    int mine = 0;
+    for (int q = 0; q < kWordsPerThread; ++q) mine += __popc(bits[threadIdx.x * kWordsPerThread + q]);
+    int total;
+    int pos = block_excl_scan(mine, red, total);
+    if (FILL) {
+      int* out = fine + fptr[tile] + emitted;
+      for (int q = 0; q < kWordsPerThread; ++q) {
+        const int wi = threadIdx.x * kWordsPerThread + q;
+        unsigned b = bits[wi];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          out[pos++] = (int)(wb + wi * 32 + bit);
+        }
+      }
+    }
+    emitted += total;
+    __syncthreads();
+  }
+  if (!FILL && threadIdx.x == 0) {
+    cnt_out[tile] = emitted;
+    rmax_out[tile] = rmax;
+  }
+}
+
+hipError_t launch_tile_fine(const int* pt_ptr, const int* pt_row, const int* tile_row0,
+                            int ntiles, int n, const int* r, bool fill, int* cnt_out,
+                            int* rmax_out, const int* fptr, int* fine, hipStream_t s) {
+  (void)n;
+  if (ntiles <= 0) return hipSuccess;
+  if (fill)
+    hipLaunchKernelGGL(k_tile_fine<true>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
+                       tile_row0, r, cnt_out, rmax_out, fptr, fine);
+  else
+    hipLaunchKernelGGL(k_tile_fine<false>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
+                       tile_row0, r, cnt_out, rmax_out, fptr, fine);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Numeric, atomic fold (F1): one wavefront per fine row I in row order.  R_I is formed in a hash
+// map (Alg. 3), then for every selected P(I,i) the lanes walk C's column list of row i, look the
+// column up in R_I and add P(I,i) * R_I(j) to C at that slot with a device-wide FP64 atomic
+// (Eq. allatonceoutproduct, the outer product of row I of P and row I of AP).
+// =============================================================================================
+template <bool G>
+__global__ __launch_bounds__(kThreads) void k_atomic_numeric(NumericArgs a,
+                                                             const int* __restrict__ rows,
+                                                             int count, int cap, int* gtab,
+                                                             double* gval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem) + wid;
+  int* keys;
+  double* vals;
+  if (G) {
+    keys = gtab + (size_t)gw * cap;
+    vals = gval + (size_t)gw * cap;
+  } else {
+    unsigned char* base = smem + kWavesPerBlock * sizeof(WaveScratch);
+    vals = reinterpret_cast<double*>(base) + (size_t)wid * cap;
+    keys = reinterpret_cast<int*>(base + (size_t)kWavesPerBlock * cap * sizeof(double)) + wid * cap;
+  }
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  const Patterns& p = a.p;
+  table_clear<G>(keys, vals, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int I = rows[r];
+    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+    bool any = false;
+    for (int e = p0 + ln; e < p1; e += WAVE) any |= part_takes(a.part, I, p.P_col[e], p.n, p.m, a.K);
+    if (!ballot(any)) continue;  // empty P_o / P_d row: skipped (Alg. 8, 10)
+    for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, a.A_val, p.P_rowptr, ws,
+                 [&](int k, double av) { hm_add<G>(keys, vals, mask, shift, p.P_col[k], av * a.P_val[k]); });
+    if constexpr (G) __threadfence();
+    for (int pb = p0; pb < p1; pb += WAVE) {
+      const int e = pb + ln;
+      const bool ok = e < p1 && part_takes(a.part, I, p.P_col[e], p.n, p.m, a.K);
+      unsigned long long mk = ballot(ok);
+      const int my_i = ok ? p.P_col[e] : 0;
+      const double my_w = ok ? a.P_val[e] : 0.0;
+      while (mk) {
+        const int src = __ffsll((long long)mk) - 1;
+        mk &= mk - 1;
+        const int i = __shfl(my_i, src, WAVE);
+        const double w = __shfl(my_w, src, WAVE);
+        for (int c = a.C_rowptr[i] + ln; c < a.C_rowptr[i + 1]; c += WAVE) {
+          const int s = hs_find<G>(keys, mask, shift, a.C_col[c]);
+          if (s >= 0) unsafeAtomicAdd(a.C_val + c, w * ld_val<G>(vals + s));
+        }
+      }
+    }
+    table_clear<G>(keys, vals, cap);
+  }
+}
+
+static size_t map_lds_bytes(int cap) {
+  return kWavesPerBlock * (sizeof(WaveScratch) + (size_t)cap * (sizeof(int) + sizeof(double)));
+}
+
+hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
+                                 hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  if (rc.global)
+    hipLaunchKernelGGL(k_atomic_numeric<true>, dim3(grid), dim3(kThreads),
+                       kWavesPerBlock * sizeof(WaveScratch), s, a, rc.rows, rc.count, rc.cap, gtab,
+                       gval);
+  else
+    hipLaunchKernelGGL(k_atomic_numeric<false>, dim3(grid), dim3(kThreads), map_lds_bytes(rc.cap), s,
+                       a, rc.rows, rc.count, rc.cap, gtab, gval);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Numeric, owner fold (F2): a workgroup owns a tile of contiguous C rows [i0, i1) whose values
+// live in LDS.  Its wavefronts take the tile's fine rows I in turn, form R_I in a per-wavefront
+// hash map, and for every P(I,i) with i in the tile add P(I,i) * R_I(j) into the tile's copy of
+// row i (LDS atomics; slots found by walking row i's columns and looking each up in R_I).  The
+// tile is written to C once, coalesced.  No device-wide atomics.
+// =============================================================================================
+template <bool HG, bool TG>
+__global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
+                                                            const int* __restrict__ tiles,
+                                                            const int* __restrict__ tile_row0,
+                                                            const int* __restrict__ tile_fptr,
+                                                            const int* __restrict__ tile_fine,
+                                                            int cap, int TE, int TR, int xcd_remap,
+                                                            int* gtab, double* gval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  int b = blockIdx.x;
+  if (xcd_remap) {
+    // Workgroups are dispatched to the 8 XCDs round-robin; give XCD x a contiguous run of tiles
+    // so neighbouring tiles (which share fine rows) meet in the same L2.
+    const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
+    b = x * q + min(x, rem) + k;
+  }
+  const int tile = tiles[b];
+  const int i0 = tile_row0[tile], i1 = tile_row0[tile + 1];
+  const int c0 = a.C_rowptr[i0];
+  const int ne = a.C_rowptr[i1] - c0;
+  const Patterns& p = a.p;
+
+  unsigned char* sp = smem;
+  double* tv;
+  const int* tc;
+  int* trp = nullptr;
+  if (TG) {
+    tv = a.C_val + c0;
+    tc = a.C_col + c0;
+  } else {
+    tv = reinterpret_cast<double*>(sp);
+    sp += (size_t)TE * sizeof(double);
+    int* tcw = reinterpret_cast<int*>(sp);
+    sp += (size_t)TE * sizeof(int);
+    trp = reinterpret_cast<int*>(sp);
+    sp += (((size_t)TR + 1) * sizeof(int) + 15) / 16 * 16;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      tv[e] = 0.0;
+      tcw[e] = a.C_col[c0 + e];
+    }
+    for (int q = threadIdx.x; q <= i1 - i0; q += blockDim.x) trp[q] = a.C_rowptr[i0 + q] - c0;
+    tc = tcw;
+  }
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(sp) + wid;
+  sp += kWavesPerBlock * sizeof(WaveScratch);
+  int* keys;
+  double* vals;
+  if (HG) {
+    const int gw = blockIdx.x * kWavesPerBlock + wid;
+    keys = gtab + (size_t)gw * cap;
+    vals = gval + (size_t)gw * cap;
+  } else {
+    vals = reinterpret_cast<double*>(sp) + (size_t)wid * cap;
+    sp += (size_t)kWavesPerBlock * cap * sizeof(double);
+    keys = reinterpret_cast<int*>(sp) + (size_t)wid * cap;
+  }
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  table_clear<HG>(keys, vals, cap);
+  __syncthreads();
+
+  const int f1 = tile_fptr[tile + 1];
+  // a.part < 0: the two passes of Alg. 8 (off-block entries, then on-block entries, R_I formed
+  // in each); otherwise one pass over the given part.
+  const int npass = a.part < 0 ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+  const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
+  for (int f = tile_fptr[tile] + wid; f < f1; f += kWavesPerBlock) {
+    const int I = tile_fine[f];
+    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+    bool any = false;
+    for (int e = p0 + ln; e < p1; e += WAVE) {
+      const int i = p.P_col[e];
+      any |= i >= i0 && i < i1 && part_takes(part, I, i, p.n, p.m, a.K);
+    }
+    if (!ballot(any)) continue;
+    for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, a.A_val, p.P_rowptr, ws,
+                 [&](int k, double av) { hm_add<HG>(keys, vals, mask, shift, p.P_col[k], av * a.P_val[k]); });
+    if constexpr (HG) __threadfence();
+    for (int pb = p0; pb < p1; pb += WAVE) {
+      const int e = pb + ln;
+      int my_i = 0;
+      bool ok = false;
+      if (e < p1) {
+        my_i = p.P_col[e];
+        ok = my_i >= i0 && my_i < i1 && part_takes(part, I, my_i, p.n, p.m, a.K);
+      }
+      unsigned long long mk = ballot(ok);
+      const double my_w = ok ? a.P_val[e] : 0.0;
+      while (mk) {
+        const int src = __ffsll((long long)mk) - 1;
+        mk &= mk - 1;
+        const int il = __shfl(my_i, src, WAVE) - i0;
+        const double w = __shfl(my_w, src, WAVE);
+        const int cb = TG ? a.C_rowptr[i0 + il] - c0 : trp[il];
+        const int ce = TG ? a.C_rowptr[i0 + il + 1] - c0 : trp[il + 1];
+        for (int c = cb + ln; c < ce; c += WAVE) {
+          const int s = hs_find<HG>(keys, mask, shift, tc[c]);
+          if (s >= 0) {
+            if (TG)
+              unsafeAtomicAdd(tv + c, w * ld_val<HG>(vals + s));
+            else
+              atomicAdd(tv + c, w * ld_val<HG>(vals + s));
+          }
+        }
+      }
+    }
+    table_clear<HG>(keys, vals, cap);
+  }
+  }
+  if (!TG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) a.C_val[c0 + e] = tv[e];
+  }
+}
+
+hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
+                                const int* tile_fptr, const int* tile_fine, int tile_entries,
+                                int tile_rows, bool xcd_remap, int* gtab, double* gval,
+                                hipStream_t s) {
+  if (tc.count == 0) return hipSuccess;
+  size_t lds = kWavesPerBlock * sizeof(WaveScratch);
+  if (!tc.tile_global)
+    lds += (size_t)tile_entries * (sizeof(double) + sizeof(int)) +
+           (((size_t)tile_rows + 1) * sizeof(int) + 15) / 16 * 16;
+  if (!tc.hash_global) lds += (size_t)kWavesPerBlock * tc.cap * (sizeof(double) + sizeof(int));
+  // Spill tables are indexed by workgroup, so a spill class launches exactly its tiles and the
+  // workspace holds one table per wavefront of the largest spill class.
+  const int grid = tc.count;
+  const int remap = xcd_remap ? 1 : 0;
+#define PTAP_LAUNCH_OWN(HG, TG)                                                                \
+  hipLaunchKernelGGL((k_owner_numeric<HG, TG>), dim3(grid), dim3(kThreads), lds, s, a, tc.tiles, \
+                     tile_row0, tile_fptr, tile_fine, tc.cap, tile_entries, tile_rows, remap,    \
+                     gtab, gval)
+  if (tc.hash_global) {
+    if (tc.tile_global) PTAP_LAUNCH_OWN(true, true); else PTAP_LAUNCH_OWN(true, false);
+  } else {
+    if (tc.tile_global) PTAP_LAUNCH_OWN(false, true); else PTAP_LAUNCH_OWN(false, false);
+  }
+#undef PTAP_LAUNCH_OWN
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Two-step numeric (Alg. 6): stored AP by rows (Alg. 4), the values of the explicit transpose
+// of P, and C = P^T (AP) by rows of P^T.
+// =============================================================================================
+template <bool G>
+__global__ __launch_bounds__(kThreads) void k_ap_numeric(NumericArgs a, const int* __restrict__ rows,
+                                                         int count, int cap,
+                                                         const int* __restrict__ AP_rowptr,
+                                                         const int* __restrict__ AP_col,
+                                                         double* AP_val, int* gtab, double* gval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem) + wid;
+  int* keys;
+  double* vals;
+  if (G) {
+    keys = gtab + (size_t)gw * cap;
+    vals = gval + (size_t)gw * cap;
+  } else {
+    unsigned char* base = smem + kWavesPerBlock * sizeof(WaveScratch);
+    vals = reinterpret_cast<double*>(base) + (size_t)wid * cap;
+    keys = reinterpret_cast<int*>(base + (size_t)kWavesPerBlock * cap * sizeof(double)) + wid * cap;
+  }
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  const Patterns& p = a.p;
+  table_clear<G>(keys, vals, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int I = rows[r];
+    for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, a.A_val, p.P_rowptr, ws,
+                 [&](int k, double av) { hm_add<G>(keys, vals, mask, shift, p.P_col[k], av * a.P_val[k]); });
+    if constexpr (G) __threadfence();
+    for (int e = AP_rowptr[I] + ln; e < AP_rowptr[I + 1]; e += WAVE) {
+      const int sl = hs_find<G>(keys, mask, shift, AP_col[e]);
+      AP_val[e] = sl >= 0 ? ld_val<G>(vals + sl) : 0.0;
+    }
+    table_clear<G>(keys, vals, cap);
+  }
+}
+
+hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int* AP_rowptr,
+                             const int* AP_col, double* AP_val, int* gtab, double* gval,
+                             hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  if (rc.global)
+    hipLaunchKernelGGL(k_ap_numeric<true>, dim3(grid), dim3(kThreads),
+                       kWavesPerBlock * sizeof(WaveScratch), s, a, rc.rows, rc.count, rc.cap,
+                       AP_rowptr, AP_col, AP_val, gtab, gval);
+  else
+    hipLaunchKernelGGL(k_ap_numeric<false>, dim3(grid), dim3(kThreads), map_lds_bytes(rc.cap), s, a,
+                       rc.rows, rc.count, rc.cap, AP_rowptr, AP_col, AP_val, gtab, gval);
+  return hipGetLastError();
+}
+
+__global__ void k_gather(const double* __restrict__ src, const int* __restrict__ idx,
+                         double* __restrict__ dst, long long count) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < count;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[k] = src[idx[k]];
+}
+
+hipError_t launch_gather(const double* src, const int* idx, double* dst, long long count,
+                         hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, src, idx, dst,
+                     count);
+  return hipGetLastError();
+}
+
+template <bool G>
+__global__ __launch_bounds__(kThreads) void k_ptc_numeric(
+    const int* __restrict__ pt_ptr, const int* __restrict__ pt_row,
+    const double* __restrict__ PT_val, const int* __restrict__ AP_rowptr,
+    const int* __restrict__ AP_col, const double* __restrict__ AP_val,
+    const int* __restrict__ C_rowptr, const int* __restrict__ C_col, double* C_val,
+    const int* __restrict__ rows, int count, int cap, int* gtab, double* gval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  int* keys;
+  double* vals;
+  if (G) {
+    keys = gtab + (size_t)gw * cap;
+    vals = gval + (size_t)gw * cap;
+  } else {
+    vals = reinterpret_cast<double*>(smem) + (size_t)wid * cap;
+    keys = reinterpret_cast<int*>(smem + (size_t)kWavesPerBlock * cap * sizeof(double)) + wid * cap;
+  }
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  table_clear<G>(keys, vals, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int i = rows[r];
+    for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
+      const int I = pt_row[t];
+      const double w = PT_val[t];
+      for (int e = AP_rowptr[I] + ln; e < AP_rowptr[I + 1]; e += WAVE)
+        hm_add<G>(keys, vals, mask, shift, AP_col[e], w * AP_val[e]);
+    }
+    if constexpr (G) __threadfence();
+    for (int c = C_rowptr[i] + ln; c < C_rowptr[i + 1]; c += WAVE) {
+      const int sl = hs_find<G>(keys, mask, shift, C_col[c]);
+      C_val[c] = sl >= 0 ? ld_val<G>(vals + sl) : 0.0;
+    }
+    table_clear<G>(keys, vals, cap);
+  }
+}
+
+hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double* PT_val,
+                              const int* AP_rowptr, const int* AP_col, const double* AP_val,
+                              const int* C_rowptr, const int* C_col, double* C_val,
+                              const RowClass& rc, int* gtab, double* gval, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  const size_t lds = rc.global ? 0 : (size_t)kWavesPerBlock * rc.cap * (sizeof(int) + sizeof(double));
+  if (rc.global)
+    hipLaunchKernelGGL(k_ptc_numeric<true>, dim3(grid), dim3(kThreads), lds, s, pt_ptr, pt_row,
+                       PT_val, AP_rowptr, AP_col, AP_val, C_rowptr, C_col, C_val, rc.rows, rc.count,
+                       rc.cap, gtab, gval);
+  else
+    hipLaunchKernelGGL(k_ptc_numeric<false>, dim3(grid), dim3(kThreads), lds, s, pt_ptr, pt_row,
+                       PT_val, AP_rowptr, AP_col, AP_val, C_rowptr, C_col, C_val, rc.rows, rc.count,
+                       rc.cap, gtab, gval);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Adjoint (dL/dA and dL/dP of L with dL/dC = dC), one wavefront per fine row I:
+//   U_I = sum_{i in P(I,:)} P(I,i) dC(i,:)           (hash map over coarse columns j)
+//   R_I = A(I,:) P                                   (hash map, formed again)
+//   for each product (J, j) of row I:  dA(I,J) += U_I(j) P(J,j),  dP(J,j) += A(I,J) U_I(j)
+//   for each P(I,k): dP(I,k) += sum_j R_I(j) dC(k,j)  (walk C's row k, look up R_I)
+// which are the entries of P dC P^T on A's pattern and of A P dC^T + A^T P dC on P's pattern.
+// dP must be zeroed first (it receives device-wide atomic adds).
+// =============================================================================================
+template <bool G>
+__global__ __launch_bounds__(kThreads) void k_backward(NumericArgs a, const double* __restrict__ dC,
+                                                       double* dA, double* dP,
+                                                       const int* __restrict__ rows, int count,
+                                                       int cap, int* gtab, double* gval) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int gw = blockIdx.x * kWavesPerBlock + wid;
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem) + wid;
+  double* dacc = reinterpret_cast<double*>(smem + kWavesPerBlock * sizeof(WaveScratch)) + wid * WAVE;
+  int *ukeys, *rkeys;
+  double *uvals, *rvals;
+  if (G) {
+    ukeys = gtab + (size_t)gw * 2 * cap;
+    rkeys = ukeys + cap;
+    uvals = gval + (size_t)gw * 2 * cap;
+    rvals = uvals + cap;
+  } else {
+    unsigned char* base = smem + kWavesPerBlock * (sizeof(WaveScratch) + WAVE * sizeof(double));
+    uvals = reinterpret_cast<double*>(base) + (size_t)wid * 2 * cap;
+    rvals = uvals + cap;
+    ukeys = reinterpret_cast<int*>(base + (size_t)kWavesPerBlock * 2 * cap * sizeof(double)) +
+            wid * 2 * cap;
+    rkeys = ukeys + cap;
+  }
+  const unsigned mask = (unsigned)cap - 1;
+  const int shift = 32 - log2_pow2(cap);
+  const Patterns& p = a.p;
+  table_clear<G>(ukeys, uvals, cap);
+  table_clear<G>(rkeys, rvals, cap);
+  for (int r = gw; r < count; r += gridDim.x * kWavesPerBlock) {
+    const int I = rows[r];
+    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+    const int a0 = p.A_rowptr[I], a1 = p.A_rowptr[I + 1];
+    // U_I
+    for (int e = p0; e < p1; ++e) {
+      const int i = p.P_col[e];
+      const double w = a.P_val[e];
+      for (int c = a.C_rowptr[i] + ln; c < a.C_rowptr[i + 1]; c += WAVE)
+        hm_add<G>(ukeys, uvals, mask, shift, a.C_col[c], w * dC[c]);
+    }
+    // R_I (only needed for the dP term of row I)
+    if (dP && p1 > p0)
+      for_products(a0, a1, p.A_col, a.A_val, p.P_rowptr, ws,
+                   [&](int k, double av) { hm_add<G>(rkeys, rvals, mask, shift, p.P_col[k], av * a.P_val[k]); });
+    if constexpr (G) __threadfence();
+    // products (J, j): dA(I,J) and the A^T P dC part of dP
+    for (int base = a0; base < a1; base += WAVE) {
+      const int t = base + ln;
+      int ps = 0, pl = 0;
+      double av = 0.0;
+      if (t < a1) {
+        const int J = p.A_col[t];
+        ps = p.P_rowptr[J];
+        pl = p.P_rowptr[J + 1] - ps;
+        av = a.A_val[t];
+      }
+      const int incl = wave_incl_scan(pl);
+      const int total = __shfl(incl, WAVE - 1, WAVE);
+      ws->off[ln] = incl - pl;
+      ws->ps[ln] = ps;
+      ws->a[ln] = av;
+      dacc[ln] = 0.0;
+      wave_sync();
+      for (int q = ln; q < total; q += WAVE) {
+        int lo = 0;
+#pragma unroll
+        for (int step = WAVE / 2; step > 0; step >>= 1)
+          if (ws->off[lo + step] <= q) lo += step;
+        const int k = ws->ps[lo] + (q - ws->off[lo]);
+        const int s = hs_find<G>(ukeys, mask, shift, p.P_col[k]);
+        if (s >= 0) {
+          const double u = ld_val<G>(uvals + s);
+          atomicAdd(dacc + lo, u * a.P_val[k]);
+          if (dP) unsafeAtomicAdd(dP + k, ws->a[lo] * u);
+        }
+      }
+      wave_sync();
+      if (dA && t < a1) dA[t] = dacc[ln];
+      wave_sync();
+    }
+    // A P dC^T part of dP: dP(I,k) += sum_j R_I(j) dC(k,j)
+    if (dP) {
+      for (int e = p0; e < p1; ++e) {
+        const int k = p.P_col[e];
+        double sum = 0.0;
+        for (int c = a.C_rowptr[k] + ln; c < a.C_rowptr[k + 1]; c += WAVE) {
+          const int s = hs_find<G>(rkeys, mask, shift, a.C_col[c]);
+          if (s >= 0) sum += ld_val<G>(rvals + s) * dC[c];
+        }
+        sum = wave_sum(sum);
+        if (ln == 0) unsafeAtomicAdd(dP + e, sum);
+      }
+    }
+    table_clear<G>(ukeys, uvals, cap);
+    table_clear<G>(rkeys, rvals, cap);
+  }
+}
+
+hipError_t launch_backward(const NumericArgs& a, const double* dC, double* dA, double* dP,
+                           const RowClass& rc, int* gtab, double* gval, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  const int grid = wave_grid(rc.count, rc.global);
+  size_t lds = kWavesPerBlock * (sizeof(WaveScratch) + WAVE * sizeof(double));
+  if (!rc.global) lds += (size_t)kWavesPerBlock * 2 * rc.cap * (sizeof(int) + sizeof(double));
+  if (rc.global)
+    hipLaunchKernelGGL(k_backward<true>, dim3(grid), dim3(kThreads), lds, s, a, dC, dA, dP, rc.rows,
+                       rc.count, rc.cap, gtab, gval);
+  else
+    hipLaunchKernelGGL(k_backward<false>, dim3(grid), dim3(kThreads), lds, s, a, dC, dA, dP, rc.rows,
+                       rc.count, rc.cap, gtab, gval);
+  return hipGetLastError();
+}
+
+}  // namespace ptapk

@@ -1,0 +1,126 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+The C pattern must be bit-exact (row pointers and sorted columns).  Values are bit-exact on
+dyadic inputs (constant-coefficient stencils with trilinear interpolation: every product and
+partial sum is exact in FP64) and otherwise within the FP64 criterion of tests/helpers.py."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import ptap_inputs as gen
+
+pytestmark = pytest.mark.gpu
+
+ALGO_FOLD = [("merged", "owner"), ("allatonce", "owner"), ("merged", "atomic"),
+             ("allatonce", "atomic"), ("twostep", "auto")]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from gpu_util import check_against_oracle  # noqa: E402
+
+
+@pytest.mark.parametrize("algo,fold", ALGO_FOLD)
+@pytest.mark.parametrize("K", [1, 3, 8])
+def test_c1_bit_exact(algo, fold, K):
+    A, P, _ = gen.galerkin_workload("c1")
+    check_against_oracle(A, P, exact=True, algo=algo, fold=fold, nblocks=K)
+
+
+@pytest.mark.parametrize("algo,fold", ALGO_FOLD)
+def test_toy_rowwise(algo, fold):
+    A, P = gen.toy_rowwise(seed=4)
+    check_against_oracle(A, P, algo=algo, fold=fold, nblocks=3)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("algo,fold", ALGO_FOLD)
+def test_random_fuzz(seed, algo, fold):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 300))
+    m = int(rng.integers(1, 60))
+    A = gen.random_csr(n, n, float(rng.uniform(0.005, 0.05)), seed=seed, empty_rows=0.1,
+                       explicit_zeros=0.05)
+    P = gen.random_csr(n, m, float(rng.uniform(0.01, 0.15)), seed=900 + seed, empty_rows=0.15,
+                       zero_cols=2 if m > 4 else 0, explicit_zeros=0.05)
+    check_against_oracle(A, P, algo=algo, fold=fold, nblocks=int(rng.integers(1, 5)))
+
+
+@pytest.mark.parametrize("algo,fold", ALGO_FOLD)
+@pytest.mark.parametrize("case", ["c2_20", "c3a_12", "c3b_9", "c3c_6"])
+def test_workloads_reduced(algo, fold, case):
+    A, P = _case(case)
+    check_against_oracle(A, P, algo=algo, fold=fold)
+
+
+@pytest.mark.parametrize("algo,fold", [("merged", "owner"), ("merged", "atomic"), ("twostep", "auto")])
+def test_forced_spill(algo, fold):
+    """Hash tables capped at 64 slots: rows with more keys go to tables in device memory."""
+    A, P = _case("c3b_9")
+    check_against_oracle(A, P, algo=algo, fold=fold, hash_slots=64)
+
+
+@pytest.mark.parametrize("tile_entries", [16, 100, 700])
+def test_owner_tile_sizes(tile_entries):
+    """Small tiles: many tiles, rows longer than a tile go to device-memory tiles."""
+    A, P = _case("c3b_9")
+    check_against_oracle(A, P, algo="merged", fold="owner", tile_entries=tile_entries)
+    A, P, _ = gen.galerkin_workload("c1")
+    check_against_oracle(A, P, exact=True, algo="allatonce", fold="owner", nblocks=4,
+                         tile_entries=tile_entries)
+
+
+@pytest.mark.parametrize("xcd", [False, True])
+def test_xcd_remap_same_result(xcd):
+    A, P, _ = gen.galerkin_workload("c1")
+    check_against_oracle(A, P, exact=True, algo="merged", fold="owner", xcd_remap=xcd, tile_entries=300)
+
+
+def test_edge_single_and_empty():
+    A = gen.CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0]))
+    P = gen.CSR(1, 1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+    for algo, fold in ALGO_FOLD:
+        check_against_oracle(A, P, exact=True, algo=algo, fold=fold)
+    # A with no entries: C has no entries at all
+    A = gen.CSR(5, 5, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    P = gen.random_csr(5, 3, 0.5, seed=1)
+    for algo, fold in ALGO_FOLD:
+        check_against_oracle(A, P, algo=algo, fold=fold)
+
+
+def test_repeated_numeric_new_values():
+    """One symbolic, several numerics with new values (Section 4.1 runs 1 + 11)."""
+    from gpu_util import GpuProblem
+    A, P = _case("c2_20")
+    g = GpuProblem(A, P)
+    plan = g.plan(algo="merged")
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        Av = rng.uniform(-1, 1, A.nnz)
+        Pv = rng.uniform(-1, 1, P.nnz)
+        g.A_val.copy_(torch.from_numpy(Av))
+        g.P_val.copy_(torch.from_numpy(Pv))
+        C = plan.numeric(g.A_val, g.P_val).cpu().numpy()
+        ref = oracle.ptap(A.with_values(Av), P.with_values(Pv))
+        from helpers import assert_close
+        assert_close(C, ref.val, ref.abs)
+    plan.close()
+
+
+def _case(case):
+    kind, s = case.rsplit("_", 1)
+    s = int(s)
+    if kind == "c2":
+        return gen.stencil27(s, seed=1), gen.trilinear(s)
+    if kind in ("c3a", "c3b"):
+        A = gen.stencil27(s, seed=2, eps_z=0.01)
+        return A, gen.smoothed_aggregation(A, s, s, s, steps=1 if kind == "c3a" else 2)
+    if kind == "c3c":
+        A = gen.block_stencil27(s, 4, seed=2)
+        return A, gen.block_smoothed_aggregation(A, s, 4)
+    raise KeyError(case)
