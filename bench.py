@@ -1,0 +1,261 @@
+"""Benchmark of the numeric triple product C = P^T A P on one MI355X.
+
+Workload (timed step): the geometric multigrid level of a 128^3 27-point operator with
+lognormal(0,1) cell coefficients (seed 1) and trilinear interpolation to 64^3, in FP64 CSR.
+One step is one numeric all-at-once product (merged form, K = 1, owner fold): every value of
+C is computed from the values of A and P, with the symbolic phase done once beforehand, as the
+paper runs one symbolic and many numerics (Section 4.1).  All inputs are resident in HBM
+before the timed region.
+
+value = algorithmic bytes of one numeric product / time per step, where the algorithmic bytes
+read A and P once (int32 column + FP64 value + int32 row pointer) and write C's values once:
+    B = 12 nnz(A) + 4 (n+1) + 12 nnz(P) + 4 (n+1) + 8 nnz(C).
+
+Printed beside it (one JSON line): the roofline of the dominant kernel, the CPU oracle on the
+host, the symbolic time, the two-step method, the all-at-once / merged forms with K = 8
+virtual blocks, the atomic fold, peak extra device memory of each algorithm, and forward +
+backward time of the differentiable form on a 64^3 problem.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(n, nnzA, nnzP, nnzC):
+    return 12 * nnzA + 4 * (n + 1) + 12 * nnzP + 4 * (n + 1) + 8 * nnzC
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--side", type=int, default=128, help="fine grid side of the timed workload")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline numeric (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of known size (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1905_08423_amd as lib
+    import ptap_inputs as gen
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        x = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+        return
+
+    t0 = time.time()
+    side = args.side
+    A = gen.stencil27(side, seed=1)
+    P = gen.trilinear(side)
+    gen_s = time.time() - t0
+    n, m = A.n_rows, P.n_cols
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    A_rowptr, A_col, A_val = d(A.rowptr, torch.int32), d(A.col, torch.int32), d(A.val, torch.float64)
+    P_rowptr, P_col, P_val = d(P.rowptr, torch.int32), d(P.col, torch.int32), d(P.val, torch.float64)
+    torch.cuda.synchronize()
+    print(f"# workload {side}^3 27-point -> {gen.coarse_side(side)}^3: n={n} m={m} nnzA={A.nnz} "
+          f"nnzP={P.nnz} (generated in {gen_s:.1f}s)", file=sys.stderr, flush=True)
+
+    def make_plan(**kw):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        ts = time.perf_counter()
+        plan = lib.Plan(n, m, A_rowptr, A_col, P_rowptr, P_col, **kw)
+        torch.cuda.synchronize()
+        sym_ms = (time.perf_counter() - ts) * 1e3
+        C = plan.numeric(A_val, P_val)
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated()
+        st = plan.stats()
+        c_bytes = 8 * st["nnz_C"] + st["pattern_bytes"]
+        extra = peak - base - c_bytes
+        return plan, C, sym_ms, extra
+
+    def time_numeric(plan, C, steps, warmup):
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            plan.numeric(A_val, P_val, C)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t_start = time.perf_counter()
+        for e0, e1 in evs:
+            e0.record(stream)
+            plan.numeric(A_val, P_val, C)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t_start) * 1e3 / steps
+        per = [e0.elapsed_time(e1) for e0, e1 in evs]
+        return wall_ms, float(np.mean(per)), float(np.min(per))
+
+    # ---------------- headline: merged (K = 1) owner fold
+    plan, C, sym_ms, extra_aao = make_plan(algo="merged", fold="owner", nblocks=1)
+    st = plan.stats()
+    nnzC = st["nnz_C"]
+    B = algorithmic_bytes(n, A.nnz, P.nnz, nnzC)
+    wall_ms, ev_ms, ev_min = time_numeric(plan, C, args.steps, args.warmup)
+    value = B / (wall_ms * 1e-3) / 1e9
+    achieved = B / (ev_ms * 1e-3) / 1e9
+    print(f"# headline numeric: {wall_ms:.3f} ms/step wall, {ev_ms:.3f} ms mean / {ev_min:.3f} ms min "
+          f"per launch (events) -> {value:.0f} GB/s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "PtAP numeric GB/s & % HBM roofline; fwd+bwd ms; peak extra mem vs two-step",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"galerkin_{side}^3_27pt_lognormal_seed1_trilinear_to_{gen.coarse_side(side)}^3",
+                   "algo": "merged all-at-once (K=1, owner fold)", "n": n, "m": m, "nnz_A": A.nnz,
+                   "nnz_P": P.nnz, "nnz_C": nnzC, "algorithmic_bytes": B},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_owner_numeric", "launch_ms_mean": round(ev_ms, 4),
+                     "launch_ms_min": round(ev_min, 4)},
+        "symbolic_ms": round(sym_ms, 2),
+        "rows_formed_per_numeric": st["rows_formed"],
+        "rows_needed": st["rows_needed"],
+        "fold_terms": st["fold_terms"],
+        "n_tiles": st["n_tiles"],
+        "peak_extra_mb": {"merged_owner": round(extra_aao / 2**20, 2)},
+    }
+    plan.close()
+    del C
+
+    if not args.headline_only:
+        variants = [("allatonce_K8_owner", dict(algo="allatonce", fold="owner", nblocks=8)),
+                    ("merged_K8_owner", dict(algo="merged", fold="owner", nblocks=8)),
+                    ("merged_atomic", dict(algo="merged", fold="atomic", nblocks=1)),
+                    ("twostep", dict(algo="twostep"))]
+        cmp_ms, cmp_sym = {}, {}
+        for name, kw in variants:
+            p2, C2, s_ms, extra = make_plan(**kw)
+            w_ms, e_ms, _ = time_numeric(p2, C2, max(3, args.steps // 4), 2)
+            cmp_ms[name] = round(e_ms, 4)
+            cmp_sym[name] = round(s_ms, 2)
+            out["peak_extra_mb"][name] = round(extra / 2**20, 2)
+            if name == "allatonce_K8_owner":
+                out["rows_formed_allatonce_K8"] = p2.stats()["rows_formed"]
+            print(f"# {name}: numeric {e_ms:.3f} ms, symbolic {s_ms:.1f} ms, peak extra {extra / 2**20:.1f} MB",
+                  file=sys.stderr, flush=True)
+            p2.close()
+            del C2
+            torch.cuda.empty_cache()
+        out["numeric_ms"] = {"merged_owner": round(ev_ms, 4), **cmp_ms}
+        out["symbolic_ms_by_algo"] = cmp_sym
+        out["memory_ratio_twostep_over_allatonce"] = round(
+            out["peak_extra_mb"]["twostep"] / max(out["peak_extra_mb"]["merged_owner"], 1e-9), 2)
+        out["fwd_bwd_ms"] = fwd_bwd(lib, gen, torch, dev)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, P, B)
+
+    print(json.dumps(out), flush=True)
+
+
+def fwd_bwd(lib, gen, torch, dev, side=64):
+    """Forward numeric + backward (dA, dP) through the autograd function on a 64^3 27-point
+    lognormal (seed 4) problem with trilinear interpolation to 32^3, loss sum(W o C)."""
+    A = gen.stencil27(side, seed=4)
+    P = gen.trilinear(side)
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    plan = lib.Plan(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
+                    d(P.rowptr, torch.int32), d(P.col, torch.int32), algo="merged", backward=True)
+    W = d(gen.loss_weights(plan.nnz_C, seed=5), torch.float64)
+    Av = d(A.val, torch.float64).requires_grad_(True)
+    Pv = d(P.val, torch.float64).requires_grad_(True)
+
+    def step():
+        Av.grad = None
+        Pv.grad = None
+        C = lib.ptap(plan, Av, Pv)
+        (C * W).sum().backward()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    reps = 10
+    t = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t) * 1e3 / reps
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    Cf = torch.empty(plan.nnz_C, dtype=torch.float64, device=dev)
+    e0.record(s)
+    for _ in range(reps):
+        plan.numeric(Av.detach(), Pv.detach(), Cf)
+    e1.record(s)
+    torch.cuda.synchronize()
+    fwd = e0.elapsed_time(e1) / reps
+    e0.record(s)
+    for _ in range(reps):
+        plan.backward(Av.detach(), Pv.detach(), W)
+    e1.record(s)
+    torch.cuda.synchronize()
+    bwd = e0.elapsed_time(e1) / reps
+    plan.close()
+    return {"workload": f"{side}^3_27pt_lognormal_seed4_trilinear_to_{gen.coarse_side(side)}^3",
+            "fwd_bwd_ms_autograd": round(total, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4)}
+
+
+def cpu_baseline(A, P, B):
+    """The CPU oracle (plain single-threaded C, as it stands) on the same 128^3 workload."""
+    import oracle
+
+    t = time.perf_counter()
+    r = oracle.ptap(A, P)
+    secs = time.perf_counter() - t
+    reps = 1
+    while time.perf_counter() - t < 10.0 and reps < 10:
+        oracle.ptap(A, P)
+        reps += 1
+    secs = (time.perf_counter() - t) / reps
+    return {"value": round(B / secs / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"full workload (all {P.n_cols} rows of C, {r.nnz} entries), {reps} run(s), "
+                      f"{secs:.2f} s each, one thread",
+            "seconds": round(secs, 3), "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

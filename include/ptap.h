@@ -91,7 +91,10 @@ typedef struct ptap_options {
   int32_t xcd_remap;     /* nonzero: map workgroups to tiles so that consecutive tiles run on
                             the same XCD (shared L2 for their common fine rows) */
   int32_t backward;      /* nonzero: also prepare the adjoint (ptap_backward) at symbolic time */
-  int32_t reserved[8];
+  int32_t owner_waves;   /* owner fold: wavefronts per workgroup, 4, 8 or 16 (0: default 16) */
+  int32_t tile_lds;      /* owner fold: LDS bytes per workgroup the tiles are sized for
+                            (0: default 80 KiB, two workgroups per CU; capped by the device) */
+  int32_t reserved[6];
 } ptap_options;
 
 typedef struct ptap_stats {

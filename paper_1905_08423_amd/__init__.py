@@ -43,7 +43,8 @@ class ptap_options(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("fold", ctypes.c_int32), ("nblocks", ctypes.c_int32),
                 ("tile_entries", ctypes.c_int32), ("hash_slots", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("backward", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("backward", ctypes.c_int32), ("owner_waves", ctypes.c_int32),
+                ("tile_lds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class ptap_stats(ctypes.Structure):
@@ -250,7 +251,7 @@ class Plan:
 
     def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
                  nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
-                 backward=False, allocator=None, stream=None):
+                 backward=False, owner_waves=0, tile_lds=0, allocator=None, stream=None):
         load_library()
         self.n, self.m = int(n), int(m)
         self.A_rowptr, self.A_col = A_rowptr, A_col
@@ -266,6 +267,8 @@ class Plan:
         o.validate = 1 if validate else 0
         o.xcd_remap = 1 if xcd_remap else 0
         o.backward = 1 if backward else 0
+        o.owner_waves = int(owner_waves)
+        o.tile_lds = int(tile_lds)
         self.options = o
         self.handle = None
         st, h = ptap_plan_create(self.n, self.m, A_rowptr, A_col, self.A_nnz, P_rowptr, P_col,

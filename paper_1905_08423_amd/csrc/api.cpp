@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <map>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ptap.h"
@@ -142,6 +143,8 @@ struct ptap_plan {
   long long nnzA = 0, nnzP = 0;
   bool sym_done = false;
   int lds_budget = 65536;
+  int lds_device = 65536;  // LDS bytes one workgroup may use on this device
+  int owner_waves = kFastWaves;
   int lds_hash_max = kLdsHashMax;
   int lds_keys_max = kLdsKeysMax;
 
@@ -243,7 +246,9 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
   if (opts) o = *opts;
   if (o.algo < PTAP_ALLATONCE || o.algo > PTAP_TWOSTEP) return PTAP_ERR_INPUT;
   if (o.fold < PTAP_FOLD_AUTO || o.fold > PTAP_FOLD_OWNER) return PTAP_ERR_INPUT;
-  if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0) return PTAP_ERR_INPUT;
+  if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0 || o.tile_lds < 0) return PTAP_ERR_INPUT;
+  if (o.owner_waves != 0 && o.owner_waves != 4 && o.owner_waves != 8 && o.owner_waves != 16)
+    return PTAP_ERR_INPUT;
   if (o.hash_slots && (o.hash_slots < 64 || (o.hash_slots & (o.hash_slots - 1)))) return PTAP_ERR_INPUT;
   if (alloc && (!alloc->alloc || !alloc->release)) return PTAP_ERR_INPUT;
 
@@ -259,6 +264,7 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
     hipck(hipGetDevice(&dev));
     hipck(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     p->lds_budget = std::min(lds, 65536);
+    p->lds_device = lds;
     if (o.hash_slots) {
       p->lds_hash_max = std::min(p->lds_hash_max, (int)o.hash_slots);
       p->lds_keys_max = std::min(p->lds_keys_max, (int)o.hash_slots);
@@ -469,16 +475,33 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
     } else {
-      // Tiles of contiguous C rows, sized for the LDS budget.
-      int rmax_all = 0;
-      for (int I = 0; I < n; ++I) rmax_all = std::max(rmax_all, hr[I]);
+      // Tiles of contiguous C rows held in LDS.  Tiles whose fine rows are short (|R_I| and
+      // the rows of P within the short-row limits) take the short-row kernel; the tile size is
+      // set by that kernel's LDS layout when every row qualifies.
+      int rmax_all = 0, pmax_all = 0;
+      {
+        std::vector<int> hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
+        for (int I = 0; I < n; ++I) {
+          rmax_all = std::max(rmax_all, hr[I]);
+          pmax_all = std::max(pmax_all, std::max(hP_rowptr[I + 1] - hP_rowptr[I],
+                                                 hA_rowptr[I + 1] - hA_rowptr[I]));
+        }
+      }
+      const bool fast_all = rmax_all <= kFastMaxKeys && pmax_all <= kFastMaxKeys;
+      const int nw = P->opt.owner_waves ? P->opt.owner_waves : kFastWaves;
+      if (nw != 4 && nw != 8 && nw != 16) fail(PTAP_ERR_INPUT);
+      P->owner_waves = nw;
+      const int lds_tile = std::min(P->lds_device, P->opt.tile_lds ? P->opt.tile_lds : kTileLdsTarget);
+      const int TR = 1024;
       const int cap_all = std::min(cap_for(rmax_all), lmax);
-      int TE = P->opt.tile_entries ? P->opt.tile_entries : kDefaultTileEntries;
-      const int TR = std::min(std::max(TE, 1), 1024);
-      const long long fixed = (long long)kWavesPerBlock * (sizeof(WaveScratch) + (long long)cap_all * 12) +
-                              ((long long)TR + 1) * 4 + 16;
-      const long long room = (P->lds_budget - fixed) / 12;
-      TE = (int)std::max<long long>(16, std::min<long long>(TE, room));
+      long long room;
+      if (fast_all)
+        room = ((long long)lds_tile - (long long)nw * (long long)owner_fast_wave_bytes() - (TR + 1) * 4LL - 16) / 12;
+      else
+        room = ((long long)lds_tile - (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) + (long long)cap_all * 12) -
+                (TR + 1) * 4LL - 16) / 12;
+      int TE = (int)std::max<long long>(16, room);
+      if (P->opt.tile_entries) TE = std::min(TE, (int)P->opt.tile_entries);
       P->TE = TE;
       P->TR = TR;
       std::vector<int> row0;
@@ -509,11 +532,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->tile_row0 = t.get<int>(T + 1);
       to_device(P->tile_row0, row0, s);
       int* tcnt = t.get<int>(T);
-      int* trmax = t.get<int>(T);
-      hipck(launch_tile_fine(P->pt_ptr, P->pt_row, P->tile_row0, T, n, r, false, tcnt, trmax,
+      int* trmax = t.get<int>(2 * (size_t)T);
+      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, P->tile_row0, T, r, false, tcnt, trmax,
                              nullptr, nullptr, s));
       std::vector<int> hcnt = to_host(tcnt, T, s);
-      std::vector<int> hrmax = to_host(trmax, T, s);
+      std::vector<int> hrmax = to_host(trmax, 2 * (size_t)T, s);
       t.put(tcnt);
       t.put(trmax);
       std::vector<int> fptr(T + 1, 0);
@@ -526,24 +549,32 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->tile_fptr = t.get<int>(T + 1);
       P->tile_fine = t.get<int>(acc);
       to_device(P->tile_fptr, fptr, s);
-      hipck(launch_tile_fine(P->pt_ptr, P->pt_row, P->tile_row0, T, n, r, true, nullptr, nullptr,
+      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, P->tile_row0, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, s));
       P->rows_formed = acc;
-      // classes by (hash capacity, placement)
-      std::map<std::pair<int, int>, std::vector<int>> groups;
+      // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
+      // its (empty) rows are written
+      std::map<std::tuple<int, int, int>, std::vector<int>> groups;
       for (int k = 0; k < T; ++k) {
-        if (hcnt[k] == 0) {
-          // no fine row touches the tile: its rows of C are empty or must be zero; still launched
-          // so that the tile writes its zeros.
+        const int rm = hrmax[2 * k], lm = hrmax[2 * k + 1];
+        const bool fast = !tglob[k] && rm <= kFastMaxKeys && lm <= kFastMaxKeys &&
+                          owner_fast_lds_bytes(TE, TR, nw) <= (size_t)P->lds_device;
+        const int cap = cap_for(std::max(rm, 1));
+        int tg = tglob[k];
+        if (!fast && !tg) {
+          const long long need = (long long)TE * 12 + (TR + 1) * 4LL + 16 +
+                                 (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) +
+                                                              (cap <= lmax ? (long long)cap * 12 : 0));
+          if (need > P->lds_device) tg = 1;
         }
-        const int cap = cap_for(std::max(hrmax[k], 1));
-        groups[{cap, (int)tglob[k]}].push_back(k);
+        groups[std::make_tuple(fast ? 1 : 0, fast ? 0 : cap, tg)].push_back(k);
       }
       for (auto& kv : groups) {
         TileClass tc;
-        tc.cap = kv.first.first;
-        tc.hash_global = tc.cap > lmax;
-        tc.tile_global = kv.first.second != 0;
+        tc.fast = std::get<0>(kv.first) != 0;
+        tc.cap = tc.fast ? 64 : std::get<1>(kv.first);
+        tc.hash_global = !tc.fast && tc.cap > lmax;
+        tc.tile_global = std::get<2>(kv.first) != 0;
         tc.count = (int)kv.second.size();
         tc.tiles = t.get<int>(tc.count);
         to_device(tc.tiles, kv.second, s);
@@ -607,6 +638,7 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
     fresh.nnzA = plan->nnzA;
     fresh.nnzP = plan->nnzP;
     fresh.lds_budget = plan->lds_budget;
+    fresh.lds_device = plan->lds_device;
     fresh.lds_hash_max = plan->lds_hash_max;
     fresh.lds_keys_max = plan->lds_keys_max;
     plan->~ptap_plan();
@@ -670,9 +702,14 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
     }
     if (P->any_tile_global) hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));
     NumericArgs a = numeric_args(P, A_val, P_val, C_val, twopass ? -1 : PART_ALL);
-    for (auto& c : P->tclasses)
-      hipck(launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
-                                 P->opt.xcd_remap != 0, P->gtab, P->gval, s));
+    for (auto& c : P->tclasses) {
+      if (c.fast)
+        hipck(launch_owner_fast(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+                                P->owner_waves, P->opt.xcd_remap != 0, s));
+      else
+        hipck(launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+                                   P->opt.xcd_remap != 0, P->gtab, P->gval, s));
+    }
   } catch (const Failure& f) {
     return f.status;
   }

@@ -34,6 +34,7 @@ struct TileClass {
   int cap = 0;
   bool hash_global = false;
   bool tile_global = false;
+  bool fast = false;     // short-row kernel (owner.hip)
   int count = 0;
   int* tiles = nullptr;  // device, tile ids
 };
@@ -42,7 +43,8 @@ struct TileClass {
 constexpr int kWavesPerBlock = 4;
 constexpr int kLdsHashMax = 1024;       // largest LDS table (slots) of a numeric kernel
 constexpr int kLdsKeysMax = 2048;       // largest LDS key-only table (slots) of a symbolic kernel
-constexpr int kDefaultTileEntries = 4096;
+constexpr int kDefaultTileEntries = 4096;  // general kernel
+constexpr int kTileLdsTarget = 81920;     // bytes of LDS per owner workgroup (two per CU)
 constexpr int kSpillWaves = 512;        // concurrent wavefronts of a spill (global-table) launch
 
 // ---------------------------------------------------------------------------------------
@@ -66,8 +68,10 @@ hipError_t launch_c_bound(const int* pt_ptr, const int* pt_row, const int* r, in
 hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row,
                          const int* AP_rowptr, const int* AP_col, const RowClass& rc, bool fill,
                          int* cnt_out, const int* C_rowptr, int* C_col, int* gtab, hipStream_t s);
-hipError_t launch_tile_fine(const int* pt_ptr, const int* pt_row, const int* tile_row0,
-                            int ntiles, int n, const int* r, bool fill, int* cnt_out,
+// Count pass: cnt_out[t] = number of distinct fine rows of tile t; rmax_out[2t] = max |R_I| and
+// rmax_out[2t+1] = max row length of A and of P over them.  Fill pass: the sorted rows.
+hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
+                            const int* tile_row0, int ntiles, const int* r, bool fill, int* cnt_out,
                             int* rmax_out, const int* fptr, int* fine, hipStream_t s);
 
 struct NumericArgs {
@@ -86,6 +90,15 @@ hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const
                                 const int* tile_fptr, const int* tile_fine, int tile_entries,
                                 int tile_rows, bool xcd_remap, int* gtab, double* gval,
                                 hipStream_t s);
+// Short-row owner kernel (owner.hip): tiles whose fine rows have |R_I| <= 32 and at most 32
+// entries in their rows of A and of P.
+constexpr int kFastMaxKeys = 32;
+constexpr int kFastWaves = 16;
+size_t owner_fast_wave_bytes();
+size_t owner_fast_lds_bytes(int TE, int TR, int nw);
+hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
+                             const int* tile_fptr, const int* tile_fine, int TE, int TR, int nw,
+                             bool xcd_remap, hipStream_t s);
 // Two-step numeric pieces.
 hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int* AP_rowptr,
                              const int* AP_col, double* AP_val, int* gtab, double* gval,

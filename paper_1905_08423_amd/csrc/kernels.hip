@@ -389,24 +389,32 @@ template <bool FILL>
 __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict__ pt_ptr,
                                                           const int* __restrict__ pt_row,
                                                           const int* __restrict__ tile_row0,
-                                                          const int* __restrict__ r, int* cnt_out,
-                                                          int* rmax_out,
+                                                          const int* __restrict__ r,
+                                                          const int* __restrict__ A_rowptr,
+                                                          const int* __restrict__ P_rowptr,
+                                                          int* cnt_out, int* rmax_out,
                                                           const int* __restrict__ fptr,
                                                           int* fine) {
   __shared__ unsigned bits[kWindowBits / 32];
   __shared__ int red[kTileBlock / WAVE];
   const int tile = blockIdx.x;
   const int t0 = pt_ptr[tile_row0[tile]], t1 = pt_ptr[tile_row0[tile + 1]];
-  int lo = INT32_MAX, hi = -1, rmax = 0;
+  int lo = INT32_MAX, hi = -1, rmax = 0, lmax = 0;
   for (int t = t0 + threadIdx.x; t < t1; t += kTileBlock) {
     const int I = pt_row[t];
     lo = min(lo, I);
     hi = max(hi, I);
-    if (!FILL) rmax = max(rmax, r[I]);
+    if (!FILL) {
+      rmax = max(rmax, r[I]);
+      lmax = max(lmax, max(A_rowptr[I + 1] - A_rowptr[I], P_rowptr[I + 1] - P_rowptr[I]));
+    }
   }
   lo = block_reduce_min(lo, red);
   hi = block_reduce_max(hi, red);
-  if (!FILL) rmax = block_reduce_max(rmax, red);
+  if (!FILL) {
+    rmax = block_reduce_max(rmax, red);
+    lmax = block_reduce_max(lmax, red);
+  }
   int emitted = 0;
   for (long long wb = lo; wb <= hi; wb += kWindowBits) {
     for (int w = threadIdx.x; w < kWindowBits / 32; w += kTileBlock) bits[w] = 0u;
@@ -438,21 +446,21 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
   }
   if (!FILL && threadIdx.x == 0) {
     cnt_out[tile] = emitted;
-    rmax_out[tile] = rmax;
+    rmax_out[2 * tile] = rmax;
+    rmax_out[2 * tile + 1] = lmax;
   }
 }
 
-hipError_t launch_tile_fine(const int* pt_ptr, const int* pt_row, const int* tile_row0,
-                            int ntiles, int n, const int* r, bool fill, int* cnt_out,
+hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
+                            const int* tile_row0, int ntiles, const int* r, bool fill, int* cnt_out,
                             int* rmax_out, const int* fptr, int* fine, hipStream_t s) {
-  (void)n;
   if (ntiles <= 0) return hipSuccess;
   if (fill)
     hipLaunchKernelGGL(k_tile_fine<true>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
-                       tile_row0, r, cnt_out, rmax_out, fptr, fine);
+                       tile_row0, r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
   else
     hipLaunchKernelGGL(k_tile_fine<false>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
-                       tile_row0, r, cnt_out, rmax_out, fptr, fine);
+                       tile_row0, r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
   return hipGetLastError();
 }
 

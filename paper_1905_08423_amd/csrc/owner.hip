@@ -1,0 +1,242 @@
+// Numeric all-at-once / merged product with the owner fold, short-row form.
+//
+// A workgroup of NW wavefronts owns a tile of contiguous rows [i0, i1) of C whose values and
+// column indices are held in LDS.  Each wavefront takes two fine rows I of the tile's list at a
+// time, one per 32-lane half:
+//   1. lane `sub` of the half loads A(I, a0+sub) and the extent of row J = A_col of P, then
+//      loads every P(J, :) entry of that row at once and inserts A(I,J) * P(J,j) into the half's
+//      hash map R_I (Alg. 3; compare-and-swap on the key, then an LDS FP64 add);
+//   2. the entries P(I,i) with i in the tile (and in the pass's part, Alg. 8 / Alg. 10) are
+//      compacted with a ballot;
+//   3. for each such i the half walks C's row i in LDS, looks every column up in R_I and adds
+//      P(I,i) * R_I(j) into the tile (Eq. allatonceoutproduct restricted to the owned rows).
+// The tile is written to C once at the end.  Used when every fine row of the tile has at most
+// 32 entries in A and in P and |R_I| <= 32; other tiles take the general kernel.  Consecutive
+// row pairs of a wavefront are software-pipelined (see the loop).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ptapk {
+
+namespace {
+constexpr int kHalf = 32;
+constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
+constexpr int kCapShift = 32 - 6;
+
+struct HalfScratch {
+  int keys[2][kCap];
+  double vals[2][kCap];
+  int sel_i[2][kHalf];
+  double sel_w[2][kHalf];
+};
+}  // namespace
+
+size_t owner_fast_wave_bytes() { return sizeof(HalfScratch); }
+
+// Per-lane state of one fine row at the successive stages of the pipelined loop (one row per
+// 32-lane half; lane `sub` follows the row's A entry a0+sub and P entry p0+sub).
+struct Stage2 {   // row extents known
+  int I;          // fine row, or -1 past the end of the tile's list
+  int t;          // a0 + sub if that A entry exists, else -1
+  int e;          // p0 + sub if that P entry exists, else -1
+};
+struct Stage3 {   // column of this lane's A entry and of its P entry known
+  int I, J, t, pi, e;  // J = column of A(I,t) (or -1); pi = column of P(I,e) (or -1)
+};
+struct Stage4 {   // extent of row J of P known
+  int I, ps, pe, t, pi, e;
+};
+
+__device__ __forceinline__ int st_header(const int* __restrict__ fine, int fr, int f1) {
+  return fr < f1 ? fine[fr] : -1;
+}
+__device__ __forceinline__ Stage2 st_rows(int I, const Patterns& p, int sub) {
+  Stage2 r{I, -1, -1};
+  if (I >= 0) {
+    const int a0 = p.A_rowptr[I], a1 = p.A_rowptr[I + 1];
+    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+    r.t = a0 + sub < a1 ? a0 + sub : -1;
+    r.e = p0 + sub < p1 ? p0 + sub : -1;
+  }
+  return r;
+}
+__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p) {
+  Stage3 r{q.I, -1, q.t, -1, q.e};
+  if (q.t >= 0) r.J = p.A_col[q.t];
+  if (q.e >= 0) r.pi = p.P_col[q.e];
+  return r;
+}
+__device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Patterns& p) {
+  Stage4 r{q.I, 0, 0, q.t, q.pi, q.e};
+  if (q.J >= 0) {
+    r.ps = p.P_rowptr[q.J];
+    r.pe = p.P_rowptr[q.J + 1];
+  }
+  return r;
+}
+
+__device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
+  unsigned s = hslot(key, kCapShift);
+  while (true) {
+    const int old = atomicCAS(keys + s, EMPTY, key);
+    if (old == EMPTY || old == key) break;
+    s = (s + 1) & (kCap - 1);
+  }
+  atomicAdd(vals + s, v);
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
+                                                             const int* __restrict__ tile_row0,
+                                                             const int* __restrict__ tile_fptr,
+                                                             const int* __restrict__ tile_fine, int TE,
+                                                             int TR, int xcd_remap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int half = ln / kHalf, sub = ln % kHalf;
+  int b = blockIdx.x;
+  if (xcd_remap) {
+    const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
+    b = x * q + min(x, rem) + k;
+  }
+  const int tile = tiles[b];
+  const int i0 = tile_row0[tile], i1 = tile_row0[tile + 1];
+  const int c0 = a.C_rowptr[i0];
+  const int ne = a.C_rowptr[i1] - c0;
+  const Patterns& p = a.p;
+
+  double* tv = reinterpret_cast<double*>(smem);
+  int* tc = reinterpret_cast<int*>(smem + (size_t)TE * sizeof(double));
+  int* trp = tc + TE;
+  HalfScratch* hs = reinterpret_cast<HalfScratch*>(
+                        smem + (((size_t)TE * 12 + ((size_t)TR + 1) * 4 + 15) / 16) * 16) +
+                    wid;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    tv[e] = 0.0;
+    tc[e] = a.C_col[c0 + e];
+  }
+  for (int q = threadIdx.x; q <= i1 - i0; q += blockDim.x) trp[q] = a.C_rowptr[i0 + q] - c0;
+  int* keys = hs->keys[half];
+  double* vals = hs->vals[half];
+  keys[sub] = EMPTY;
+  keys[sub + kHalf] = EMPTY;
+  vals[sub] = 0.0;
+  vals[sub + kHalf] = 0.0;
+  __syncthreads();
+
+  const int f0 = tile_fptr[tile], f1 = tile_fptr[tile + 1];
+  const int step = 2 * NW;
+  const int npass = a.part < 0 ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
+    // Software pipeline over the wavefront's row pairs f, f+step, f+2*step, ...: while the
+    // pair being folded (cur) works in LDS, the next pairs advance one load stage each (row
+    // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
+    // load overlaps one iteration of LDS work instead of stalling the wavefront.
+    const int fb = f0 + 2 * wid + half;
+    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), p, sub), p), p);
+    Stage3 nxt = st_entries(st_rows(st_header(tile_fine, fb + step, f1), p, sub), p);
+    Stage2 nn = st_rows(st_header(tile_fine, fb + 2 * step, f1), p, sub);
+    for (int f = f0 + 2 * wid; f < f1; f += step) {
+      // (1) values of cur's A and P entries and its first four products (the rest load in (4))
+      const double cav = cur.t >= 0 ? a.A_val[cur.t] : 0.0;
+      const double cpw = cur.e >= 0 ? a.P_val[cur.e] : 0.0;
+      int jj[4];
+      double pv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (cur.ps + u < cur.pe) {
+          jj[u] = p.P_col[cur.ps + u];
+          pv[u] = a.P_val[cur.ps + u];
+        }
+      }
+      // (2) one load stage for each following pair
+      const Stage4 nxt4 = st_pext(nxt, p);
+      const Stage3 nn3 = st_entries(nn, p);
+      const Stage2 nnn2 = st_rows(st_header(tile_fine, f + 3 * step + half, f1), p, sub);
+      // (3) owned entries of P(I,:) of cur, compacted per half
+      const bool in_t = cur.pi >= i0 && cur.pi < i1 && part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
+      const unsigned long long bal = ballot(in_t);
+      const unsigned hm = half ? (unsigned)(bal >> 32) : (unsigned)bal;
+      const int nsel = __popc(hm);
+      if (in_t) {
+        const int pos = __popc(hm & ((1u << sub) - 1u));
+        hs->sel_i[half][pos] = cur.pi - i0;
+        hs->sel_w[half][pos] = cpw;
+      }
+      const int nmax = max(nsel, __shfl_xor(nsel, kHalf, WAVE));
+      // (4) R_I of cur in the half's hash map
+      if (nsel > 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (cur.ps + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
+        for (int k0 = cur.ps + 4; k0 < cur.pe; k0 += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (k0 + u < cur.pe) {
+              jj[u] = p.P_col[k0 + u];
+              pv[u] = a.P_val[k0 + u];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (k0 + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
+        }
+      }
+      wave_sync();
+      // (6) fold the owned part of P(I,:) (x) R_I into the tile
+      for (int kk = 0; kk < nmax; ++kk) {
+        if (kk < nsel) {
+          const int rl = hs->sel_i[half][kk];
+          const double wk = hs->sel_w[half][kk];
+          const int ce = trp[rl + 1];
+          for (int c = trp[rl] + sub; c < ce; c += kHalf) {
+            const int j = tc[c];
+            unsigned s = hslot(j, kCapShift);
+            int kf;
+            while ((kf = keys[s]) != j && kf != EMPTY) s = (s + 1) & (kCap - 1);
+            if (kf == j) atomicAdd(tv + c, wk * vals[s]);
+          }
+        }
+      }
+      wave_sync();
+      if (nsel > 0) {
+        keys[sub] = EMPTY;
+        keys[sub + kHalf] = EMPTY;
+        vals[sub] = 0.0;
+        vals[sub + kHalf] = 0.0;
+      }
+      wave_sync();
+      cur = nxt4;
+      nxt = nn3;
+      nn = nnn2;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) a.C_val[c0 + e] = tv[e];
+}
+
+size_t owner_fast_lds_bytes(int TE, int TR, int nw) {
+  return (((size_t)TE * 12 + ((size_t)TR + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
+}
+
+hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
+                             const int* tile_fptr, const int* tile_fine, int TE, int TR, int nw,
+                             bool xcd_remap, hipStream_t s) {
+  if (tc.count == 0) return hipSuccess;
+  const size_t lds = owner_fast_lds_bytes(TE, TR, nw);
+  const int remap = xcd_remap ? 1 : 0;
+  if (nw == 16) {
+    hipLaunchKernelGGL(k_owner_fast<16>, dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
+                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+  } else if (nw == 8) {
+    hipLaunchKernelGGL(k_owner_fast<8>, dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
+                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+  } else {
+    hipLaunchKernelGGL(k_owner_fast<4>, dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
+                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ptapk

@@ -124,3 +124,13 @@ def _case(case):
         A = gen.block_stencil27(s, 4, seed=2)
         return A, gen.block_smoothed_aggregation(A, s, 4)
     raise KeyError(case)
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+@pytest.mark.parametrize("algo,K", [("merged", 1), ("allatonce", 4)])
+def test_owner_waves(waves, algo, K):
+    """The short-row owner kernel with each workgroup size (and the two-pass form)."""
+    A, P, _ = gen.galerkin_workload("c1")
+    check_against_oracle(A, P, exact=True, algo=algo, fold="owner", nblocks=K, owner_waves=waves)
+    A, P = _case("c2_20")
+    check_against_oracle(A, P, algo=algo, fold="owner", nblocks=K, owner_waves=waves, tile_entries=500)
