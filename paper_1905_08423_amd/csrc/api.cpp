@@ -487,7 +487,9 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
                                                  hA_rowptr[I + 1] - hA_rowptr[I]));
         }
       }
-      const bool fast_all = rmax_all <= kFastMaxKeys && pmax_all <= kFastMaxKeys;
+      // the short-row kernel addresses P's arrays and the row pointers with 32-bit byte offsets
+      const bool fast_fits = P->nnzP * 8 < (1LL << 31) && ((long long)n + 1) * 4 < (1LL << 31);
+      const bool fast_all = fast_fits && rmax_all <= kFastMaxKeys && pmax_all <= kFastMaxKeys;
       const int nw = P->opt.owner_waves ? P->opt.owner_waves : kFastWaves;
       if (nw != 4 && nw != 8 && nw != 16) fail(PTAP_ERR_INPUT);
       P->owner_waves = nw;
@@ -557,7 +559,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       std::map<std::tuple<int, int, int>, std::vector<int>> groups;
       for (int k = 0; k < T; ++k) {
         const int rm = hrmax[2 * k], lm = hrmax[2 * k + 1];
-        const bool fast = !tglob[k] && rm <= kFastMaxKeys && lm <= kFastMaxKeys &&
+        const bool fast = fast_fits && !tglob[k] && rm <= kFastMaxKeys && lm <= kFastMaxKeys &&
                           owner_fast_lds_bytes(TE, TR, nw) <= (size_t)P->lds_device;
         const int cap = cap_for(std::max(rm, 1));
         int tg = tglob[k];

@@ -33,6 +33,22 @@ struct HalfScratch {
 
 size_t owner_fast_wave_bytes() { return sizeof(HalfScratch); }
 
+// Raw buffer resources: 32-bit byte offsets instead of 64-bit addresses, and one 8- or 16-byte
+// load per lane for a pair of row pointers or four entries of a row of P.  (Each lane reads its
+// own row of P, so the cost of a load is set by the number of distinct cache lines it touches:
+// one wide load costs about what one 4-byte load costs.)
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+constexpr int kRawBufferFlags = 0x00020000;  // 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           kRawBufferFlags);
+}
+__device__ __forceinline__ v2u ld_pair(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_amdgcn_raw_buffer_load_b64(r, idx * 4, 0, 0);
+}
+
 // Per-lane state of one fine row at the successive stages of the pipelined loop (one row per
 // 32-lane half; lane `sub` follows the row's A entry a0+sub and P entry p0+sub).
 struct Stage2 {   // row extents known
@@ -50,11 +66,12 @@ struct Stage4 {   // extent of row J of P known
 __device__ __forceinline__ int st_header(const int* __restrict__ fine, int fr, int f1) {
   return fr < f1 ? fine[fr] : -1;
 }
-__device__ __forceinline__ Stage2 st_rows(int I, const Patterns& p, int sub) {
+__device__ __forceinline__ Stage2 st_rows(int I, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rP,
+                                          int sub) {
   Stage2 r{I, -1, -1};
   if (I >= 0) {
-    const int a0 = p.A_rowptr[I], a1 = p.A_rowptr[I + 1];
-    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+    const v2u ar = ld_pair(rA, I), pr = ld_pair(rP, I);
+    const int a0 = (int)ar[0], a1 = (int)ar[1], p0 = (int)pr[0], p1 = (int)pr[1];
     r.t = a0 + sub < a1 ? a0 + sub : -1;
     r.e = p0 + sub < p1 ? p0 + sub : -1;
   }
@@ -66,13 +83,44 @@ __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p)
   if (q.e >= 0) r.pi = p.P_col[q.e];
   return r;
 }
-__device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Patterns& p) {
+__device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP) {
   Stage4 r{q.I, 0, 0, q.t, q.pi, q.e};
   if (q.J >= 0) {
-    r.ps = p.P_rowptr[q.J];
-    r.pe = p.P_rowptr[q.J + 1];
+    const v2u pr = ld_pair(rP, q.J);
+    r.ps = (int)pr[0];
+    r.pe = (int)pr[1];
   }
   return r;
+}
+
+// Four consecutive entries k0..k0+3 of P: columns and values.  Wide loads when the whole
+// window lies inside P's arrays; otherwise entry by entry up to `ke`.
+__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rv,
+                                      const int* __restrict__ P_col, const double* __restrict__ P_val,
+                                      int k0, int ke, int nnzP, int (&jj)[4], double (&pv)[4]) {
+  if (k0 + 4 <= nnzP) {
+    const v4i c = __builtin_amdgcn_raw_buffer_load_b128(rc, k0 * 4, 0, 0);
+    const v4i v01 = __builtin_amdgcn_raw_buffer_load_b128(rv, k0 * 8, 0, 0);
+    const v4i v23 = __builtin_amdgcn_raw_buffer_load_b128(rv, k0 * 8 + 16, 0, 0);
+    jj[0] = c[0];
+    jj[1] = c[1];
+    jj[2] = c[2];
+    jj[3] = c[3];
+    pv[0] = __hiloint2double(v01[1], v01[0]);
+    pv[1] = __hiloint2double(v01[3], v01[2]);
+    pv[2] = __hiloint2double(v23[1], v23[0]);
+    pv[3] = __hiloint2double(v23[3], v23[2]);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      jj[u] = 0;
+      pv[u] = 0.0;
+      if (k0 + u < ke) {
+        jj[u] = P_col[k0 + u];
+        pv[u] = P_val[k0 + u];
+      }
+    }
+  }
 }
 
 __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
@@ -126,6 +174,11 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
 
   const int f0 = tile_fptr[tile], f1 = tile_fptr[tile + 1];
   const int step = 2 * NW;
+  const int nnzP = p.P_rowptr[p.n];
+  const __amdgpu_buffer_rsrc_t rA = buffer_rsrc(p.A_rowptr, (unsigned)(p.n + 1) * 4u);
+  const __amdgpu_buffer_rsrc_t rP = buffer_rsrc(p.P_rowptr, (unsigned)(p.n + 1) * 4u);
+  const __amdgpu_buffer_rsrc_t rPc = buffer_rsrc(p.P_col, (unsigned)nnzP * 4u);
+  const __amdgpu_buffer_rsrc_t rPv = buffer_rsrc(a.P_val, (unsigned)nnzP * 8u);
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
@@ -134,26 +187,20 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
     // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
     // load overlaps one iteration of LDS work instead of stalling the wavefront.
     const int fb = f0 + 2 * wid + half;
-    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), p, sub), p), p);
-    Stage3 nxt = st_entries(st_rows(st_header(tile_fine, fb + step, f1), p, sub), p);
-    Stage2 nn = st_rows(st_header(tile_fine, fb + 2 * step, f1), p, sub);
+    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), rA, rP, sub), p), rP);
+    Stage3 nxt = st_entries(st_rows(st_header(tile_fine, fb + step, f1), rA, rP, sub), p);
+    Stage2 nn = st_rows(st_header(tile_fine, fb + 2 * step, f1), rA, rP, sub);
     for (int f = f0 + 2 * wid; f < f1; f += step) {
       // (1) values of cur's A and P entries and its first four products (the rest load in (4))
       const double cav = cur.t >= 0 ? a.A_val[cur.t] : 0.0;
       const double cpw = cur.e >= 0 ? a.P_val[cur.e] : 0.0;
       int jj[4];
       double pv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (cur.ps + u < cur.pe) {
-          jj[u] = p.P_col[cur.ps + u];
-          pv[u] = a.P_val[cur.ps + u];
-        }
-      }
+      load4(rPc, rPv, p.P_col, a.P_val, cur.ps, cur.pe, nnzP, jj, pv);
       // (2) one load stage for each following pair
-      const Stage4 nxt4 = st_pext(nxt, p);
+      const Stage4 nxt4 = st_pext(nxt, rP);
       const Stage3 nn3 = st_entries(nn, p);
-      const Stage2 nnn2 = st_rows(st_header(tile_fine, f + 3 * step + half, f1), p, sub);
+      const Stage2 nnn2 = st_rows(st_header(tile_fine, f + 3 * step + half, f1), rA, rP, sub);
       // (3) owned entries of P(I,:) of cur, compacted per half
       const bool in_t = cur.pi >= i0 && cur.pi < i1 && part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
       const unsigned long long bal = ballot(in_t);
@@ -171,13 +218,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
         for (int u = 0; u < 4; ++u)
           if (cur.ps + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
         for (int k0 = cur.ps + 4; k0 < cur.pe; k0 += 4) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (k0 + u < cur.pe) {
-              jj[u] = p.P_col[k0 + u];
-              pv[u] = a.P_val[k0 + u];
-            }
-          }
+          load4(rPc, rPv, p.P_col, a.P_val, k0, cur.pe, nnzP, jj, pv);
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (k0 + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
