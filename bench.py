@@ -36,6 +36,31 @@ def algorithmic_bytes(n, nnzA, nnzP, nnzC):
     return 12 * nnzA + 4 * (n + 1) + 12 * nnzP + 4 * (n + 1) + 8 * nnzC
 
 
+PROFILE = os.path.join(ROOT, "profiles", "owner_numeric_128cubed_27pt.md")
+KERNEL_SOURCES = ["paper_1905_08423_amd/csrc/owner.hip", "paper_1905_08423_amd/csrc/device.hpp",
+                  "paper_1905_08423_amd/csrc/internal.hpp"]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the owner kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,7 +173,8 @@ def main():
                    "algo": "merged all-at-once (K=1, owner fold)", "n": n, "m": m, "nnz_A": A.nnz,
                    "nnz_P": P.nnz, "nnz_C": nnzC, "algorithmic_bytes": B},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic() if side == 128 else None,
                      "kernel": "k_owner_numeric", "launch_ms_mean": round(ev_ms, 4),
                      "launch_ms_min": round(ev_min, 4)},
         "symbolic_ms": round(sym_ms, 2),
