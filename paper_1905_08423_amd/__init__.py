@@ -355,6 +355,40 @@ def _hip():
     return _hip_lib
 
 
+class Batch:
+    """Batched numeric products over several plans (Plan objects) in one HIP graph.
+
+    levels[k] orders the work: all products of a level run together in one persistent launch,
+    after every product of a smaller level (a coarse level's A is the previous level's C).  The
+    value tensors passed to the first numeric() call are recorded into the graph: later calls
+    must pass the same tensors (their contents may change)."""
+
+    def __init__(self, plans, levels=None, allocator=None, stream=None):
+        self.plans = list(plans)
+        self.allocator = allocator if allocator is not None else TorchAllocator()
+        st, h = ptap_batch_create([p.handle for p in self.plans], levels, self.allocator.struct, stream)
+        _check(st, "ptap_batch_create")
+        self.handle = h
+        self._keep = None
+
+    def numeric(self, A_vals, P_vals, C_vals, stream=None):
+        self._keep = (list(A_vals), list(P_vals), list(C_vals))
+        _check(ptap_batch_numeric(self.handle, A_vals, P_vals, C_vals, stream), "ptap_batch_numeric")
+        return C_vals
+
+    def close(self):
+        if self.handle is not None:
+            torch.cuda.synchronize()
+            ptap_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class PtAPFunction(torch.autograd.Function):
     """C_val = PtAP(A_val, P_val) on a plan's fixed patterns; backward through ptap_backward
     (dA = P dC P^T on A's pattern, dP = A P dC^T + A^T P dC on P's pattern)."""

@@ -162,6 +162,7 @@ struct ptap_plan {
   int* tile_row0 = nullptr;
   int* tile_fptr = nullptr;
   int* tile_fine = nullptr;
+  std::vector<int> host_fptr;
   std::vector<TileClass> tclasses;
   bool any_tile_global = false;
 
@@ -192,8 +193,17 @@ struct ptap_batch {
   Tracker mem;
   std::vector<ptap_plan*> plans;
   std::vector<int> level;
-  hipGraphExec_t exec = nullptr;
+  std::vector<int> levels;                 // distinct levels, ascending
+  std::vector<std::vector<int>> level_plans;
+  std::vector<int2*> items;                // per level, device (plan, tile) work lists
+  std::vector<int> nitems;
+  int* counters = nullptr;                 // one work counter per level
+  OwnerBatchPlan* d_plans = nullptr;
+  int grid = 0;
+  size_t lds = 0;
+  hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   std::vector<const double*> A_vals, P_vals;
   std::vector<double*> C_vals;
 };
@@ -551,6 +561,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->tile_fptr = t.get<int>(T + 1);
       P->tile_fine = t.get<int>(acc);
       to_device(P->tile_fptr, fptr, s);
+      P->host_fptr = fptr;
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, P->tile_row0, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, s));
       P->rows_formed = acc;
@@ -580,6 +591,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         tc.count = (int)kv.second.size();
         tc.tiles = t.get<int>(tc.count);
         to_device(tc.tiles, kv.second, s);
+        tc.host_tiles = kv.second;
         if (tc.tile_global) P->any_tile_global = true;
         if (tc.hash_global)
           spill_need_ints = std::max(spill_need_ints, (size_t)tc.count * kWavesPerBlock * tc.cap);
@@ -641,6 +653,7 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
     fresh.nnzP = plan->nnzP;
     fresh.lds_budget = plan->lds_budget;
     fresh.lds_device = plan->lds_device;
+    fresh.owner_waves = plan->owner_waves;
     fresh.lds_hash_max = plan->lds_hash_max;
     fresh.lds_keys_max = plan->lds_keys_max;
     plan->~ptap_plan();
@@ -762,18 +775,149 @@ void ptap_plan_destroy(ptap_plan* P) {
 
 ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const int32_t* level,
                               int32_t count, const ptap_allocator* alloc, hipStream_t stream) {
-  (void)plans; (void)level; (void)count; (void)alloc; (void)stream;
-  if (out) *out = nullptr;
-  return PTAP_ERR_UNSUPPORTED;
+  if (!out) return PTAP_ERR_INPUT;
+  *out = nullptr;
+  if (count < 1 || !plans) return PTAP_ERR_INPUT;
+  if (alloc && (!alloc->alloc || !alloc->release)) return PTAP_ERR_INPUT;
+  for (int k = 0; k < count; ++k) {
+    if (!plans[k]) return PTAP_ERR_INPUT;
+    if (!plans[k]->sym_done) return PTAP_ERR_STATE;
+    if (plans[k]->opt.algo == PTAP_TWOSTEP || plans[k]->fold_used != PTAP_FOLD_OWNER)
+      return PTAP_ERR_UNSUPPORTED;
+  }
+  ptap_batch* b = new (std::nothrow) ptap_batch();
+  if (!b) return PTAP_ERR_OOM;
+  if (alloc) b->mem.a = *alloc;
+  try {
+    b->plans.assign(plans, plans + count);
+    b->level.resize(count);
+    for (int k = 0; k < count; ++k) b->level[k] = level ? level[k] : 0;
+    b->levels = b->level;
+    std::sort(b->levels.begin(), b->levels.end());
+    b->levels.erase(std::unique(b->levels.begin(), b->levels.end()), b->levels.end());
+    const int L = (int)b->levels.size();
+    b->level_plans.resize(L);
+    for (int k = 0; k < count; ++k) {
+      const int l = (int)(std::lower_bound(b->levels.begin(), b->levels.end(), b->level[k]) - b->levels.begin());
+      b->level_plans[l].push_back(k);
+    }
+    // work lists: the short-row tiles of every plan of a level, longest first
+    for (int l = 0; l < L; ++l) {
+      std::vector<std::pair<int, int2>> w;
+      for (int k : b->level_plans[l]) {
+        const ptap_plan* P = plans[k];
+        for (const TileClass& c : P->tclasses) {
+          if (!c.fast) continue;
+          for (int tl : c.host_tiles)
+            w.push_back({P->host_fptr[tl + 1] - P->host_fptr[tl], make_int2(k, tl)});
+        }
+        b->lds = std::max(b->lds, owner_fast_lds_bytes(P->TE, P->TR, kFastWaves));
+      }
+      std::stable_sort(w.begin(), w.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
+        return x.first > y.first;
+      });
+      std::vector<int2> items(w.size());
+      for (size_t q = 0; q < w.size(); ++q) items[q] = w[q].second;
+      int2* d = b->mem.get<int2>(items.size());
+      if (!items.empty()) {
+        hipck(hipMemcpyAsync(d, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, stream));
+        hipck(hipStreamSynchronize(stream));
+      }
+      b->items.push_back(d);
+      b->nitems.push_back((int)items.size());
+    }
+    b->counters = b->mem.get<int>(L);
+    b->d_plans = b->mem.get<OwnerBatchPlan>(count);
+    int dev = 0, cus = 0;
+    hipck(hipGetDevice(&dev));
+    hipck(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->grid = std::max(1, cus * 2);
+    hipck(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  } catch (const Failure& f) {
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->mem.release_all();
+    delete b;
+    return f.status;
+  }
+  *out = b;
+  return PTAP_OK;
 }
 
-ptap_status ptap_batch_numeric(ptap_batch* batch, const double* const* A_vals,
+static void batch_record(ptap_batch* b, hipStream_t s) {
+  const int count = (int)b->plans.size();
+  std::vector<OwnerBatchPlan> desc(count);
+  for (int k = 0; k < count; ++k) {
+    ptap_plan* P = b->plans[k];
+    NumericArgs a = numeric_args(P, b->A_vals[k], b->P_vals[k], b->C_vals[k],
+                                 (P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1) ? -1 : PART_ALL);
+    desc[k] = OwnerBatchPlan{a, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR};
+  }
+  hipck(hipMemcpyAsync(b->d_plans, desc.data(), desc.size() * sizeof(OwnerBatchPlan),
+                       hipMemcpyHostToDevice, s));
+  hipck(hipStreamSynchronize(s));
+  hipck(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+  hipError_t err = hipSuccess;
+  for (size_t l = 0; l < b->levels.size() && err == hipSuccess; ++l) {
+    err = launch_fill_i32(b->counters + l, 0, 1, b->cap);
+    for (int k : b->level_plans[l]) {
+      ptap_plan* P = b->plans[k];
+      const NumericArgs& a = desc[k].a;
+      if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
+      for (const TileClass& c : P->tclasses)
+        if (err == hipSuccess && !c.fast)
+          err = launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+                                     P->opt.xcd_remap != 0, P->gtab, P->gval, b->cap);
+    }
+    if (err == hipSuccess)
+      err = launch_owner_fast_batch(b->d_plans, b->items[l], b->nitems[l], b->counters + l, b->grid,
+                                    b->lds, b->cap);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t end = hipStreamEndCapture(b->cap, &g);
+  hipck(err);
+  hipck(end);
+  b->graph = g;
+  hipck(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+}
+
+ptap_status ptap_batch_numeric(ptap_batch* b, const double* const* A_vals,
                                const double* const* P_vals, double* const* C_vals,
                                hipStream_t stream) {
-  (void)batch; (void)A_vals; (void)P_vals; (void)C_vals; (void)stream;
-  return PTAP_ERR_UNSUPPORTED;
+  if (!b || !A_vals || !P_vals || !C_vals) return PTAP_ERR_INPUT;
+  const int count = (int)b->plans.size();
+  for (int k = 0; k < count; ++k) {
+    const ptap_plan* P = b->plans[k];
+    if ((!A_vals[k] && P->nnzA) || (!P_vals[k] && P->nnzP) || (!C_vals[k] && P->nnzC))
+      return PTAP_ERR_INPUT;
+  }
+  try {
+    if (!b->exec) {
+      b->A_vals.assign(A_vals, A_vals + count);
+      b->P_vals.assign(P_vals, P_vals + count);
+      b->C_vals.assign(C_vals, C_vals + count);
+      batch_record(b, stream);
+    } else {
+      for (int k = 0; k < count; ++k)
+        if (A_vals[k] != b->A_vals[k] || P_vals[k] != b->P_vals[k] || C_vals[k] != b->C_vals[k])
+          return PTAP_ERR_INPUT;
+    }
+    hipck(hipGraphLaunch(b->exec, stream));
+  } catch (const Failure& f) {
+    return f.status;
+  }
+  return PTAP_OK;
 }
 
-void ptap_batch_destroy(ptap_batch* batch) { delete batch; }
+void ptap_batch_destroy(ptap_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) {
+    (void)hipStreamSynchronize(b->cap);
+    (void)hipStreamDestroy(b->cap);
+  }
+  b->mem.release_all();
+  delete b;
+}
 
 }  // extern "C"

@@ -37,6 +37,7 @@ struct TileClass {
   bool fast = false;     // short-row kernel (owner.hip)
   int count = 0;
   int* tiles = nullptr;  // device, tile ids
+  std::vector<int> host_tiles;
 };
 
 // Limits of on-chip storage per launch (bytes of LDS per workgroup are set per kernel).
@@ -99,6 +100,16 @@ size_t owner_fast_lds_bytes(int TE, int TR, int nw);
 hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
                              const int* tile_fptr, const int* tile_fine, int TE, int TR, int nw,
                              bool xcd_remap, hipStream_t s);
+// Batched owner fold: a device-side description of one plan (values included).
+struct OwnerBatchPlan {
+  NumericArgs a;
+  const int* tile_row0;
+  const int* tile_fptr;
+  const int* tile_fine;
+  int TE, TR;
+};
+hipError_t launch_owner_fast_batch(const OwnerBatchPlan* plans, const int2* items, int nitems,
+                                   int* counter, int grid, size_t lds, hipStream_t s);
 // Two-step numeric pieces.
 hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int* AP_rowptr,
                              const int* AP_col, double* AP_val, int* gtab, double* gval,

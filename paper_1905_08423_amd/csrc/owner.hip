@@ -133,21 +133,16 @@ __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, dou
   atomicAdd(vals + s, v);
 }
 
+// One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
+// per-wavefront hash tables.  Ends with the tile written to C and a workgroup barrier.
 template <int NW>
-__global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
-                                                             const int* __restrict__ tile_row0,
-                                                             const int* __restrict__ tile_fptr,
-                                                             const int* __restrict__ tile_fine, int TE,
-                                                             int TR, int xcd_remap) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile,
+                                                const int* __restrict__ tile_row0,
+                                                const int* __restrict__ tile_fptr,
+                                                const int* __restrict__ tile_fine, int TE, int TR,
+                                                unsigned char* smem) {
   const int wid = threadIdx.x / WAVE, ln = lane();
   const int half = ln / kHalf, sub = ln % kHalf;
-  int b = blockIdx.x;
-  if (xcd_remap) {
-    const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
-    b = x * q + min(x, rem) + k;
-  }
-  const int tile = tiles[b];
   const int i0 = tile_row0[tile], i1 = tile_row0[tile + 1];
   const int c0 = a.C_rowptr[i0];
   const int ne = a.C_rowptr[i1] - c0;
@@ -255,6 +250,44 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
   }
   __syncthreads();
   for (int e = threadIdx.x; e < ne; e += blockDim.x) a.C_val[c0 + e] = tv[e];
+  __syncthreads();
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
+                                                             const int* __restrict__ tile_row0,
+                                                             const int* __restrict__ tile_fptr,
+                                                             const int* __restrict__ tile_fine, int TE,
+                                                             int TR, int xcd_remap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int b = blockIdx.x;
+  if (xcd_remap) {
+    // Workgroups are dispatched to the 8 XCDs round-robin; give XCD x a contiguous run of tiles
+    // so neighbouring tiles (which share fine rows) meet in the same L2.
+    const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
+    b = x * q + min(x, rem) + k;
+  }
+  owner_fast_tile<NW>(a, tiles[b], tile_row0, tile_fptr, tile_fine, TE, TR, smem);
+}
+
+// Batched form: a persistent grid takes (plan, tile) items from a device counter until the list
+// is exhausted; every item is one tile of one plan's owner fold.
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBatchPlan* __restrict__ plans,
+                                                                   const int2* __restrict__ items,
+                                                                   int nitems, int* counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int next;
+  while (true) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int2 w = items[it];
+    const OwnerBatchPlan& pl = plans[w.x];
+    owner_fast_tile<NW>(pl.a, w.y, pl.tile_row0, pl.tile_fptr, pl.tile_fine, pl.TE, pl.TR, smem);
+  }
 }
 
 size_t owner_fast_lds_bytes(int TE, int TR, int nw) {
@@ -277,6 +310,14 @@ hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const in
     hipLaunchKernelGGL(k_owner_fast<4>, dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
                        tile_row0, tile_fptr, tile_fine, TE, TR, remap);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_owner_fast_batch(const OwnerBatchPlan* plans, const int2* items, int nitems,
+                                   int* counter, int grid, size_t lds, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_owner_fast_batch<kFastWaves>, dim3(grid), dim3(kFastWaves * WAVE), lds, s,
+                     plans, items, nitems, counter);
   return hipGetLastError();
 }
 
