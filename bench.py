@@ -211,6 +211,7 @@ def main():
         out["memory_ratio_twostep_over_allatonce"] = round(
             out["peak_extra_mb"]["twostep"] / max(out["peak_extra_mb"]["merged_owner"], 1e-9), 2)
         out["fwd_bwd_ms"] = fwd_bwd(lib, gen, torch, dev)
+        out["batched"] = batched(lib, gen, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, P, B)
@@ -263,6 +264,93 @@ def fwd_bwd(lib, gen, torch, dev, side=64):
     plan.close()
     return {"workload": f"{side}^3_27pt_lognormal_seed4_trilinear_to_{gen.coarse_side(side)}^3",
             "fwd_bwd_ms_autograd": round(total, 4), "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4)}
+
+
+def _time_events(fn, reps, torch):
+    s = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched(lib, gen, torch, dev):
+    """The batched form against plain per-plan launches: (i) a 6-level geometric hierarchy from a
+    256^3 7-point Laplacian (trilinear P at every level, each level's A the previous C), one
+    persistent launch per level in one HIP graph; (ii) 64 independent 27-point lognormal problems
+    with grid sides uniform in 12..64 (seed 3), one persistent launch."""
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    res = {}
+    # (i) hierarchy
+    sides = gen.hierarchy_sides(256, 6)
+    A0 = gen.laplacian7(sides[0])
+    A_rowptr, A_col = d(A0.rowptr, torch.int32), d(A0.col, torch.int32)
+    A0_val = d(A0.val, torch.float64)
+    del A0
+    plans, Pv, keep = [], [], []
+    for s_ in sides[:-1]:
+        P = gen.trilinear(s_)
+        Prp, Pc = d(P.rowptr, torch.int32), d(P.col, torch.int32)
+        plan = lib.Plan(P.n_rows, P.n_cols, A_rowptr, A_col, Prp, Pc, algo="merged")
+        plans.append(plan)
+        keep.append((A_rowptr, A_col, Prp, Pc))
+        Pv.append(d(P.val, torch.float64))
+        A_rowptr, A_col = plan.pattern()
+    C = [torch.empty(p.nnz_C, dtype=torch.float64, device=dev) for p in plans]
+    Cp = [torch.empty_like(c) for c in C]
+    A_vals = [A0_val] + C[:-1]
+    A_plain = [A0_val] + Cp[:-1]
+
+    def plain_h():
+        for k, p in enumerate(plans):
+            p.numeric(A_plain[k], Pv[k], Cp[k])
+
+    batch = lib.Batch(plans, levels=list(range(len(plans))))
+    t_plain = _time_events(plain_h, 10, torch)
+    t_batch = _time_events(lambda: batch.numeric(A_vals, Pv, C), 10, torch)
+    diff = max(float(((c - cp).abs().max() / cp.abs().max().clamp_min(1e-300)).item()) for c, cp in zip(C, Cp))
+    res["hierarchy_256cubed_6_levels"] = {"products": len(plans), "plain_ms": round(t_plain, 4),
+                                          "batched_graph_ms": round(t_batch, 4),
+                                          "max_rel_diff_vs_plain": diff}
+    batch.close()
+    for p in plans:
+        p.close()
+    del C, Cp, A_vals, A_plain, keep, Pv
+    torch.cuda.empty_cache()
+    # (ii) independent problems
+    sides3 = gen.batch_problem_sides(64, seed=3, lo=12, hi=64)
+    plans, Av, Pv, keep = [], [], [], []
+    for k, (nx, ny, nz) in enumerate(sides3):
+        A = gen.stencil27(int(nx), int(ny), int(nz), seed=1000 + k)
+        P = gen.trilinear(int(nx), int(ny), int(nz))
+        t = (d(A.rowptr, torch.int32), d(A.col, torch.int32), d(P.rowptr, torch.int32), d(P.col, torch.int32))
+        keep.append(t)
+        plans.append(lib.Plan(A.n_rows, P.n_cols, *t, algo="merged"))
+        Av.append(d(A.val, torch.float64))
+        Pv.append(d(P.val, torch.float64))
+    C = [torch.empty(p.nnz_C, dtype=torch.float64, device=dev) for p in plans]
+    Cp = [torch.empty_like(c) for c in C]
+
+    def plain_i():
+        for k, p in enumerate(plans):
+            p.numeric(Av[k], Pv[k], Cp[k])
+
+    batch = lib.Batch(plans)
+    t_plain = _time_events(plain_i, 10, torch)
+    t_batch = _time_events(lambda: batch.numeric(Av, Pv, C), 10, torch)
+    diff = max(float(((c - cp).abs().max() / cp.abs().max().clamp_min(1e-300)).item()) for c, cp in zip(C, Cp))
+    res["independent_64_sides_12_64"] = {"products": len(plans), "fine_rows": int(sum(p.n for p in plans)),
+                                         "plain_ms": round(t_plain, 4), "batched_graph_ms": round(t_batch, 4),
+                                         "max_rel_diff_vs_plain": diff}
+    batch.close()
+    for p in plans:
+        p.close()
+    return res
 
 
 def cpu_baseline(A, P, B):

@@ -179,8 +179,10 @@ void ptap_plan_destroy(ptap_plan* plan);
  * Batched numeric over several plans (levels of a hierarchy or independent problems).
  * plans[k] must have finished its symbolic phase; the plans stay owned by the caller and
  * must outlive the batch.  level[k] orders the work: every product with level L runs after
- * every product with a smaller level (a coarse level's A is the previous level's C), and
- * products of one level run together in one persistent launch.  level may be NULL (all 0).
+ * every product with a smaller level (a coarse level's A is the previous level's C).  The
+ * products of one level run together in one persistent launch that takes (plan, tile) work
+ * items from per-XCD counters; a level holding a single plan uses that plan's own launch.
+ * level may be NULL (all 0).  Only plans with the owner fold can be batched.
  * The batch records its launches once into a HIP graph at the first ptap_batch_numeric call
  * and replays the graph afterwards; pointer arguments must therefore stay the same on every
  * call (their contents may change).

@@ -197,7 +197,7 @@ struct ptap_batch {
   std::vector<std::vector<int>> level_plans;
   std::vector<int2*> items;                // per level, device (plan, tile) work lists
   std::vector<int> nitems;
-  int* counters = nullptr;                 // one work counter per level
+  int* counters = nullptr;                 // per level, one work counter per XCD
   OwnerBatchPlan* d_plans = nullptr;
   int grid = 0;
   size_t lds = 0;
@@ -507,8 +507,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       const int TR = 1024;
       const int cap_all = std::min(cap_for(rmax_all), lmax);
       long long room;
+      // (256 bytes stay free for the batched kernel's own LDS variables, so that two workgroups
+      // still fit in a CU's 160 KiB)
       if (fast_all)
-        room = ((long long)lds_tile - (long long)nw * (long long)owner_fast_wave_bytes() - (TR + 1) * 4LL - 16) / 12;
+        room = ((long long)lds_tile - (long long)nw * (long long)owner_fast_wave_bytes() - (TR + 1) * 4LL - 16 -
+                256) / 12;
       else
         room = ((long long)lds_tile - (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) + (long long)cap_all * 12) -
                 (TR + 1) * 4LL - 16) / 12;
@@ -801,7 +804,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
       const int l = (int)(std::lower_bound(b->levels.begin(), b->levels.end(), b->level[k]) - b->levels.begin());
       b->level_plans[l].push_back(k);
     }
-    // work lists: the short-row tiles of every plan of a level, longest first
+    // work lists: the short-row tiles of every plan of a level, plan by plan, tiles in order
     for (int l = 0; l < L; ++l) {
       std::vector<std::pair<int, int2>> w;
       for (int k : b->level_plans[l]) {
@@ -813,9 +816,6 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
         }
         b->lds = std::max(b->lds, owner_fast_lds_bytes(P->TE, P->TR, kFastWaves));
       }
-      std::stable_sort(w.begin(), w.end(), [](const std::pair<int, int2>& x, const std::pair<int, int2>& y) {
-        return x.first > y.first;
-      });
       std::vector<int2> items(w.size());
       for (size_t q = 0; q < w.size(); ++q) items[q] = w[q].second;
       int2* d = b->mem.get<int2>(items.size());
@@ -826,7 +826,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
       b->items.push_back(d);
       b->nitems.push_back((int)items.size());
     }
-    b->counters = b->mem.get<int>(L);
+    b->counters = b->mem.get<int>((size_t)L * kXcds);
     b->d_plans = b->mem.get<OwnerBatchPlan>(count);
     int dev = 0, cus = 0;
     hipck(hipGetDevice(&dev));
@@ -858,19 +858,25 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
   hipck(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
   hipError_t err = hipSuccess;
   for (size_t l = 0; l < b->levels.size() && err == hipSuccess; ++l) {
-    err = launch_fill_i32(b->counters + l, 0, 1, b->cap);
+    err = launch_fill_i32(b->counters + l * kXcds, 0, kXcds, b->cap);
     for (int k : b->level_plans[l]) {
       ptap_plan* P = b->plans[k];
       const NumericArgs& a = desc[k].a;
       if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
-      for (const TileClass& c : P->tclasses)
-        if (err == hipSuccess && !c.fast)
+      const bool single = b->level_plans[l].size() == 1;
+      for (const TileClass& c : P->tclasses) {
+        if (err != hipSuccess) break;
+        if (!c.fast)
           err = launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
                                      P->opt.xcd_remap != 0, P->gtab, P->gval, b->cap);
+        else if (single)  // one plan at this level: its own grid, tiles mapped to XCDs in order
+          err = launch_owner_fast(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+                                  P->owner_waves, P->opt.xcd_remap != 0, b->cap);
+      }
     }
-    if (err == hipSuccess)
-      err = launch_owner_fast_batch(b->d_plans, b->items[l], b->nitems[l], b->counters + l, b->grid,
-                                    b->lds, b->cap);
+    if (err == hipSuccess && b->level_plans[l].size() > 1)
+      err = launch_owner_fast_batch(b->d_plans, b->items[l], b->nitems[l], b->counters + l * kXcds,
+                                    b->grid, b->lds, b->cap);
   }
   hipGraph_t g = nullptr;
   const hipError_t end = hipStreamEndCapture(b->cap, &g);

@@ -47,6 +47,7 @@ constexpr int kLdsKeysMax = 2048;       // largest LDS key-only table (slots) of
 constexpr int kDefaultTileEntries = 4096;  // general kernel
 constexpr int kTileLdsTarget = 81920;     // bytes of LDS per owner workgroup (two per CU)
 constexpr int kSpillWaves = 512;        // concurrent wavefronts of a spill (global-table) launch
+constexpr int kXcds = 8;                // accelerator complex dies of the MI355X
 
 // ---------------------------------------------------------------------------------------
 // Launch wrappers (kernels.hip).  All take a stream and return hipError_t.
@@ -108,8 +109,9 @@ struct OwnerBatchPlan {
   const int* tile_fine;
   int TE, TR;
 };
+// counters: kXcds work counters, zeroed before the launch
 hipError_t launch_owner_fast_batch(const OwnerBatchPlan* plans, const int2* items, int nitems,
-                                   int* counter, int grid, size_t lds, hipStream_t s);
+                                   int* counters, int grid, size_t lds, hipStream_t s);
 // Two-step numeric pieces.
 hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int* AP_rowptr,
                              const int* AP_col, double* AP_val, int* gtab, double* gval,

@@ -270,23 +270,36 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
   owner_fast_tile<NW>(a, tiles[b], tile_row0, tile_fptr, tile_fine, TE, TR, smem);
 }
 
-// Batched form: a persistent grid takes (plan, tile) items from a device counter until the list
-// is exhausted; every item is one tile of one plan's owner fold.
+// Batched form: a persistent grid works through a list of (plan, tile) items, every item one tile
+// of one plan's owner fold.  The list (plan by plan, tiles in order) is cut into 8 contiguous
+// chunks with a counter each; the workgroups of XCD x (workgroups are dispatched to the XCDs
+// round-robin) take items from chunk x, so neighbouring tiles share that XCD's L2, and then help
+// with the other chunks.
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBatchPlan* __restrict__ plans,
                                                                    const int2* __restrict__ items,
-                                                                   int nitems, int* counter) {
+                                                                   int nitems, int* counters) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int next;
-  while (true) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = next;
-    __syncthreads();
-    if (it >= nitems) break;
-    const int2 w = items[it];
-    const OwnerBatchPlan& pl = plans[w.x];
-    owner_fast_tile<NW>(pl.a, w.y, pl.tile_row0, pl.tile_fptr, pl.tile_fine, pl.TE, pl.TR, smem);
+  const int xcd = blockIdx.x % kXcds;
+  for (int c = 0; c < kXcds; ++c) {
+    const int x = (xcd + c) % kXcds;
+    const int hi = (int)(((long long)(x + 1) * nitems) / kXcds);
+    const int lo = (int)(((long long)x * nitems) / kXcds);
+    while (true) {
+      if (threadIdx.x == 0) next = lo + atomicAdd(counters + x, 1);
+      __syncthreads();
+      // the item is the same for the whole workgroup: read it into scalar registers, so the
+      // plan's pointers are loaded with scalar loads and stay out of the vector registers
+      const int it = __builtin_amdgcn_readfirstlane(next);
+      __syncthreads();
+      if (it >= hi) break;
+      const int2 w = items[it];
+      const int pk = __builtin_amdgcn_readfirstlane(w.x);
+      const int tl = __builtin_amdgcn_readfirstlane(w.y);
+      const OwnerBatchPlan& pl = plans[pk];
+      owner_fast_tile<NW>(pl.a, tl, pl.tile_row0, pl.tile_fptr, pl.tile_fine, pl.TE, pl.TR, smem);
+    }
   }
 }
 
