@@ -134,6 +134,60 @@ size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
   return need;
 }
 
+// Tiles of rows of C for the owner fold, grown breadth-first over the graph of C's pattern (row
+// r is adjacent to the columns of row r): starting from the lowest unassigned row, rows are taken
+// in BFS order while the tile holds at most TE entries and TR rows.  On meshes this gives compact
+// tiles, so fewer fine rows touch two tiles than with contiguous ranges of rows.  A row longer
+// than TE forms a tile of its own (tglob = 1: kept in device memory).  Rows within a tile are
+// listed in ascending order.
+void grow_tiles(int m, const std::vector<int>& cptr, const std::vector<int>& ccol, int TE, int TR,
+                std::vector<int>& tptr, std::vector<int>& trows, std::vector<char>& tglob) {
+  std::vector<int> state(m, -1);  // -1 free, -2 queued for the tile being grown, >= 0 tile id
+  std::vector<int> queue;
+  tptr.assign(1, 0);
+  trows.clear();
+  tglob.clear();
+  for (int seed = 0; seed < m; ++seed) {
+    if (state[seed] != -1) continue;
+    const int T = (int)tglob.size();
+    if (cptr[seed + 1] - cptr[seed] > TE) {
+      state[seed] = T;
+      trows.push_back(seed);
+      tptr.push_back((int)trows.size());
+      tglob.push_back(1);
+      continue;
+    }
+    const size_t start = trows.size();
+    queue.clear();
+    queue.push_back(seed);
+    state[seed] = -2;
+    size_t head = 0;
+    long long acc = 0;
+    int nrows = 0;
+    while (head < queue.size()) {
+      const int r = queue[head];
+      const int sz = cptr[r + 1] - cptr[r];
+      if (acc + sz > TE || nrows >= TR) break;
+      ++head;
+      acc += sz;
+      ++nrows;
+      state[r] = T;
+      trows.push_back(r);
+      for (int k = cptr[r]; k < cptr[r + 1]; ++k) {
+        const int c = ccol[k];
+        if (c >= 0 && c < m && state[c] == -1) {
+          state[c] = -2;
+          queue.push_back(c);
+        }
+      }
+    }
+    for (size_t q = head; q < queue.size(); ++q) state[queue[q]] = -1;  // not taken
+    std::sort(trows.begin() + (long)start, trows.end());
+    tptr.push_back((int)trows.size());
+    tglob.push_back(0);
+  }
+}
+
 }  // namespace
 
 struct ptap_plan {
@@ -157,9 +211,11 @@ struct ptap_plan {
   int* pt_row = nullptr;
   int* pt_pos = nullptr;
 
-  // owner fold
-  int ntiles = 0, TE = 0, TR = 0;
-  int* tile_row0 = nullptr;
+  // owner fold: tiles (row lists), the slot of every row of C, per-tile fine-row lists
+  int ntiles = 0, TE = 0;
+  int* tile_ptr = nullptr;
+  int* tile_rows = nullptr;
+  int* tile_slot = nullptr;
   int* tile_fptr = nullptr;
   int* tile_fine = nullptr;
   std::vector<int> host_fptr;
@@ -485,7 +541,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
     } else {
-      // Tiles of contiguous C rows held in LDS.  Tiles whose fine rows are short (|R_I| and
+      // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
       int rmax_all = 0, pmax_all = 0;
@@ -504,7 +560,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       if (nw != 4 && nw != 8 && nw != 16) fail(PTAP_ERR_INPUT);
       P->owner_waves = nw;
       const int lds_tile = std::min(P->lds_device, P->opt.tile_lds ? P->opt.tile_lds : kTileLdsTarget);
-      const int TR = 1024;
+      const int TR = kTileRows;
       const int cap_all = std::min(cap_for(rmax_all), lmax);
       long long room;
       // (256 bytes stay free for the batched kernel's own LDS variables, so that two workgroups
@@ -518,38 +574,27 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       int TE = (int)std::max<long long>(16, room);
       if (P->opt.tile_entries) TE = std::min(TE, (int)P->opt.tile_entries);
       P->TE = TE;
-      P->TR = TR;
-      std::vector<int> row0;
+      std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
+      std::vector<int> tptr, trows;
       std::vector<char> tglob;
-      int i = 0;
-      while (i < m) {
-        const int sz0 = h_c_ptr[i + 1] - h_c_ptr[i];
-        row0.push_back(i);
-        if (sz0 > TE) {
-          tglob.push_back(1);
-          ++i;
-          continue;
-        }
-        long long acc = 0;
-        int rows_in = 0;
-        while (i < m && rows_in < TR) {
-          const int sz = h_c_ptr[i + 1] - h_c_ptr[i];
-          if (acc + sz > TE) break;
-          acc += sz;
-          ++rows_in;
-          ++i;
-        }
-        tglob.push_back(0);
-      }
-      row0.push_back(m);
+      grow_tiles(m, h_c_ptr, h_c_col, TE, TR, tptr, trows, tglob);
       const int T = (int)tglob.size();
+      if (T >= (1 << (31 - kTileRowBits))) fail(PTAP_ERR_TOO_LARGE);
+      std::vector<int> slot(m, -1);
+      for (int k = 0; k < T; ++k)
+        for (int q = tptr[k]; q < tptr[k + 1]; ++q) slot[trows[q]] = (k << kTileRowBits) | (q - tptr[k]);
       P->ntiles = T;
-      P->tile_row0 = t.get<int>(T + 1);
-      to_device(P->tile_row0, row0, s);
+      P->tile_ptr = t.get<int>(T + 1);
+      P->tile_rows = t.get<int>(m);
+      P->tile_slot = t.get<int>(m);
+      to_device(P->tile_ptr, tptr, s);
+      to_device(P->tile_rows, trows, s);
+      to_device(P->tile_slot, slot, s);
+      const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
       int* tcnt = t.get<int>(T);
       int* trmax = t.get<int>(2 * (size_t)T);
-      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, P->tile_row0, T, r, false, tcnt, trmax,
-                             nullptr, nullptr, s));
+      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, false, tcnt, trmax, nullptr,
+                             nullptr, s));
       std::vector<int> hcnt = to_host(tcnt, T, s);
       std::vector<int> hrmax = to_host(trmax, 2 * (size_t)T, s);
       t.put(tcnt);
@@ -565,7 +610,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->tile_fine = t.get<int>(acc);
       to_device(P->tile_fptr, fptr, s);
       P->host_fptr = fptr;
-      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, P->tile_row0, T, r, true, nullptr, nullptr,
+      hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, s));
       P->rows_formed = acc;
       // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
@@ -574,15 +619,12 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       for (int k = 0; k < T; ++k) {
         const int rm = hrmax[2 * k], lm = hrmax[2 * k + 1];
         const bool fast = fast_fits && !tglob[k] && rm <= kFastMaxKeys && lm <= kFastMaxKeys &&
-                          owner_fast_lds_bytes(TE, TR, nw) <= (size_t)P->lds_device;
+                          owner_fast_lds_bytes(TE, nw) <= (size_t)P->lds_device;
         const int cap = cap_for(std::max(rm, 1));
         int tg = tglob[k];
-        if (!fast && !tg) {
-          const long long need = (long long)TE * 12 + (TR + 1) * 4LL + 16 +
-                                 (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) +
-                                                              (cap <= lmax ? (long long)cap * 12 : 0));
-          if (need > P->lds_device) tg = 1;
-        }
+        if (!fast && !tg && owner_general_lds_bytes(TE, cap, cap > lmax, false) > (size_t)P->lds_device)
+          tg = 1;
+        if (tg && tptr[k + 1] - tptr[k] != 1) fail(PTAP_ERR_UNSUPPORTED);  // a device-memory tile holds one row
         groups[std::make_tuple(fast ? 1 : 0, fast ? 0 : cap, tg)].push_back(k);
       }
       for (auto& kv : groups) {
@@ -721,11 +763,12 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
     if (P->any_tile_global) hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));
     NumericArgs a = numeric_args(P, A_val, P_val, C_val, twopass ? -1 : PART_ALL);
     for (auto& c : P->tclasses) {
+      const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
       if (c.fast)
-        hipck(launch_owner_fast(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
-                                P->owner_waves, P->opt.xcd_remap != 0, s));
+        hipck(launch_owner_fast(a, c, ts, P->tile_fptr, P->tile_fine, P->TE, P->owner_waves,
+                                P->opt.xcd_remap != 0, s));
       else
-        hipck(launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+        hipck(launch_owner_numeric(a, c, ts, P->tile_fptr, P->tile_fine, P->TE,
                                    P->opt.xcd_remap != 0, P->gtab, P->gval, s));
     }
   } catch (const Failure& f) {
@@ -814,7 +857,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
           for (int tl : c.host_tiles)
             w.push_back({P->host_fptr[tl + 1] - P->host_fptr[tl], make_int2(k, tl)});
         }
-        b->lds = std::max(b->lds, owner_fast_lds_bytes(P->TE, P->TR, kFastWaves));
+        b->lds = std::max(b->lds, owner_fast_lds_bytes(P->TE, kFastWaves));
       }
       std::vector<int2> items(w.size());
       for (size_t q = 0; q < w.size(); ++q) items[q] = w[q].second;
@@ -850,7 +893,8 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
     ptap_plan* P = b->plans[k];
     NumericArgs a = numeric_args(P, b->A_vals[k], b->P_vals[k], b->C_vals[k],
                                  (P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1) ? -1 : PART_ALL);
-    desc[k] = OwnerBatchPlan{a, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR};
+    desc[k] = OwnerBatchPlan{a, TileSet{P->tile_ptr, P->tile_rows, P->tile_slot}, P->tile_fptr,
+                             P->tile_fine, P->TE};
   }
   hipck(hipMemcpyAsync(b->d_plans, desc.data(), desc.size() * sizeof(OwnerBatchPlan),
                        hipMemcpyHostToDevice, s));
@@ -866,12 +910,13 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       const bool single = b->level_plans[l].size() == 1;
       for (const TileClass& c : P->tclasses) {
         if (err != hipSuccess) break;
+        const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
         if (!c.fast)
-          err = launch_owner_numeric(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
+          err = launch_owner_numeric(a, c, ts, P->tile_fptr, P->tile_fine, P->TE,
                                      P->opt.xcd_remap != 0, P->gtab, P->gval, b->cap);
         else if (single)  // one plan at this level: its own grid, tiles mapped to XCDs in order
-          err = launch_owner_fast(a, c, P->tile_row0, P->tile_fptr, P->tile_fine, P->TE, P->TR,
-                                  P->owner_waves, P->opt.xcd_remap != 0, b->cap);
+          err = launch_owner_fast(a, c, ts, P->tile_fptr, P->tile_fine, P->TE, P->owner_waves,
+                                  P->opt.xcd_remap != 0, b->cap);
       }
     }
     if (err == hipSuccess && b->level_plans[l].size() > 1)

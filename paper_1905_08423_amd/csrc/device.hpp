@@ -196,6 +196,66 @@ __device__ __forceinline__ void for_products(int a0, int a1, const int* __restri
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Owner tiles: a tile is a set of up to kTileRows rows of C, listed (ascending) in
+// rows[ptr[t] .. ptr[t+1]).  slot[i] = t * kTileRows + (position of row i in its tile), so a
+// single load tells whether column i of P belongs to the tile and where its row sits in LDS.
+// ------------------------------------------------------------------------------------------
+constexpr int kTileRowBits = 10;
+constexpr int kTileRows = 1 << kTileRowBits;
+
+struct TileSet {
+  const int* ptr;
+  const int* rows;
+  const int* slot;
+};
+
+// Copy a tile's rows of C into LDS: trp[q] = offset of local row q (trp[nr] = entries), tc = the
+// columns, tv = 0.  All threads of the workgroup take part; ends with a workgroup barrier.
+__device__ __forceinline__ void tile_load(const int* __restrict__ rows, int tp, int nr,
+                                          const int* __restrict__ C_rowptr,
+                                          const int* __restrict__ C_col, int* trp, int* tc,
+                                          double* tv) {
+  const int wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE, ln = lane();
+  if (wid == 0) {
+    int run = 0;
+    for (int q0 = 0; q0 < nr; q0 += WAVE) {
+      const int q = q0 + ln;
+      int len = 0;
+      if (q < nr) {
+        const int i = rows[tp + q];
+        len = C_rowptr[i + 1] - C_rowptr[i];
+      }
+      const int incl = wave_incl_scan(len);
+      if (q < nr) trp[q] = run + incl - len;
+      run += __shfl(incl, WAVE - 1, WAVE);
+    }
+    if (ln == 0) trp[nr] = run;
+  }
+  __syncthreads();
+  for (int q = wid; q < nr; q += nw) {
+    const int i = rows[tp + q];
+    const int s = C_rowptr[i], e = C_rowptr[i + 1], o = trp[q] - s;
+    for (int k = s + ln; k < e; k += WAVE) {
+      tc[o + k] = C_col[k];
+      tv[o + k] = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// Write a tile's values back to the rows of C (each row contiguous in C).
+__device__ __forceinline__ void tile_store(const int* __restrict__ rows, int tp, int nr,
+                                           const int* __restrict__ C_rowptr, const int* trp,
+                                           const double* tv, double* __restrict__ C_val) {
+  const int wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE, ln = lane();
+  for (int q = wid; q < nr; q += nw) {
+    const int i = rows[tp + q];
+    const int s = C_rowptr[i], e = C_rowptr[i + 1], o = trp[q] - s;
+    for (int k = s + ln; k < e; k += WAVE) C_val[k] = tv[o + k];
+  }
+}
+
 // Contiguous K-way split of [0, total) as in the 1D block-row partition (Section 2): block b
 // owns [floor(b*total/K), floor((b+1)*total/K)).
 __device__ __forceinline__ int block_start(int b, int total, int K) {

@@ -73,7 +73,7 @@ hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row
 // Count pass: cnt_out[t] = number of distinct fine rows of tile t; rmax_out[2t] = max |R_I| and
 // rmax_out[2t+1] = max row length of A and of P over them.  Fill pass: the sorted rows.
 hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
-                            const int* tile_row0, int ntiles, const int* r, bool fill, int* cnt_out,
+                            const TileSet& ts, int ntiles, const int* r, bool fill, int* cnt_out,
                             int* rmax_out, const int* fptr, int* fine, hipStream_t s);
 
 struct NumericArgs {
@@ -88,26 +88,26 @@ struct NumericArgs {
 };
 hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
                                  hipStream_t s);
-hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
+size_t owner_general_lds_bytes(int TE, int cap, bool hash_global, bool tile_global);
+hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
                                 const int* tile_fptr, const int* tile_fine, int tile_entries,
-                                int tile_rows, bool xcd_remap, int* gtab, double* gval,
-                                hipStream_t s);
+                                bool xcd_remap, int* gtab, double* gval, hipStream_t s);
 // Short-row owner kernel (owner.hip): tiles whose fine rows have |R_I| <= 32 and at most 32
 // entries in their rows of A and of P.
 constexpr int kFastMaxKeys = 32;
 constexpr int kFastWaves = 16;
 size_t owner_fast_wave_bytes();
-size_t owner_fast_lds_bytes(int TE, int TR, int nw);
-hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
-                             const int* tile_fptr, const int* tile_fine, int TE, int TR, int nw,
+size_t owner_fast_lds_bytes(int TE, int nw);
+hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
+                             const int* tile_fptr, const int* tile_fine, int TE, int nw,
                              bool xcd_remap, hipStream_t s);
 // Batched owner fold: a device-side description of one plan (values included).
 struct OwnerBatchPlan {
   NumericArgs a;
-  const int* tile_row0;
+  TileSet ts;
   const int* tile_fptr;
   const int* tile_fine;
-  int TE, TR;
+  int TE;
 };
 // counters: kXcds work counters, zeroed before the launch
 hipError_t launch_owner_fast_batch(const OwnerBatchPlan* plans, const int2* items, int nitems,

@@ -342,9 +342,9 @@ hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row
 }
 
 // =============================================================================================
-// Owner tiles: for each tile of contiguous C rows [i0, i1), the sorted distinct fine rows I with
-// P(I,i) stored for some i in the tile (from P's column lists), and the largest |R_I| among
-// them.  A bitmap over windows of the candidates' index span removes duplicates and emits the
+// Owner tiles: for each tile (a set of rows of C), the sorted distinct fine rows I with P(I,i)
+// stored for some i in the tile (from P's column lists), the largest |R_I| among them and the
+// longest of their rows of A and P.  A bitmap over windows of the candidates' index span removes duplicates and emits the
 // rows in ascending order.
 // =============================================================================================
 constexpr int kTileBlock = 256;
@@ -388,8 +388,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* red, int& total) {
 template <bool FILL>
 __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict__ pt_ptr,
                                                           const int* __restrict__ pt_row,
-                                                          const int* __restrict__ tile_row0,
-                                                          const int* __restrict__ r,
+                                                          TileSet ts, const int* __restrict__ r,
                                                           const int* __restrict__ A_rowptr,
                                                           const int* __restrict__ P_rowptr,
                                                           int* cnt_out, int* rmax_out,
@@ -398,15 +397,19 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
   __shared__ unsigned bits[kWindowBits / 32];
   __shared__ int red[kTileBlock / WAVE];
   const int tile = blockIdx.x;
-  const int t0 = pt_ptr[tile_row0[tile]], t1 = pt_ptr[tile_row0[tile + 1]];
+  const int tp = ts.ptr[tile], nr = ts.ptr[tile + 1] - tp;
+  // candidates: the column lists of P for every row of the tile (one thread per tile row)
   int lo = INT32_MAX, hi = -1, rmax = 0, lmax = 0;
-  for (int t = t0 + threadIdx.x; t < t1; t += kTileBlock) {
-    const int I = pt_row[t];
-    lo = min(lo, I);
-    hi = max(hi, I);
-    if (!FILL) {
-      rmax = max(rmax, r[I]);
-      lmax = max(lmax, max(A_rowptr[I + 1] - A_rowptr[I], P_rowptr[I + 1] - P_rowptr[I]));
+  for (int q = threadIdx.x; q < nr; q += kTileBlock) {
+    const int i = ts.rows[tp + q];
+    for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
+      const int I = pt_row[t];
+      lo = min(lo, I);
+      hi = max(hi, I);
+      if (!FILL) {
+        rmax = max(rmax, r[I]);
+        lmax = max(lmax, max(A_rowptr[I + 1] - A_rowptr[I], P_rowptr[I + 1] - P_rowptr[I]));
+      }
     }
   }
   lo = block_reduce_min(lo, red);
@@ -419,9 +422,12 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
   for (long long wb = lo; wb <= hi; wb += kWindowBits) {
     for (int w = threadIdx.x; w < kWindowBits / 32; w += kTileBlock) bits[w] = 0u;
     __syncthreads();
-    for (int t = t0 + threadIdx.x; t < t1; t += kTileBlock) {
-      const long long d = (long long)pt_row[t] - wb;
-      if (d >= 0 && d < kWindowBits) atomicOr(bits + (d >> 5), 1u << (d & 31));
+    for (int q = threadIdx.x; q < nr; q += kTileBlock) {
+      const int i = ts.rows[tp + q];
+      for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
+        const long long d = (long long)pt_row[t] - wb;
+        if (d >= 0 && d < kWindowBits) atomicOr(bits + (d >> 5), 1u << (d & 31));
+      }
     }
     __syncthreads();
     constexpr int kWordsPerThread = kWindowBits / 32 / kTileBlock;
@@ -433,10 +439,10 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
       int* out = fine + fptr[tile] + emitted;
       for (int q = 0; q < kWordsPerThread; ++q) {
         const int wi = threadIdx.x * kWordsPerThread + q;
-        unsigned b = bits[wi];
-        while (b) {
-          const int bit = __ffs(b) - 1;
-          b &= b - 1;
+        unsigned bw = bits[wi];
+        while (bw) {
+          const int bit = __ffs(bw) - 1;
+          bw &= bw - 1;
           out[pos++] = (int)(wb + wi * 32 + bit);
         }
       }
@@ -452,15 +458,15 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
 }
 
 hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
-                            const int* tile_row0, int ntiles, const int* r, bool fill, int* cnt_out,
+                            const TileSet& ts, int ntiles, const int* r, bool fill, int* cnt_out,
                             int* rmax_out, const int* fptr, int* fine, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fill)
-    hipLaunchKernelGGL(k_tile_fine<true>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
-                       tile_row0, r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
+    hipLaunchKernelGGL(k_tile_fine<true>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row, ts,
+                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
   else
-    hipLaunchKernelGGL(k_tile_fine<false>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row,
-                       tile_row0, r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
+    hipLaunchKernelGGL(k_tile_fine<false>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row, ts,
+                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
   return hipGetLastError();
 }
 
@@ -542,19 +548,20 @@ hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* 
 }
 
 // =============================================================================================
-// Numeric, owner fold (F2): a workgroup owns a tile of contiguous C rows [i0, i1) whose values
-// live in LDS.  Its wavefronts take the tile's fine rows I in turn, form R_I in a per-wavefront
-// hash map, and for every P(I,i) with i in the tile add P(I,i) * R_I(j) into the tile's copy of
-// row i (LDS atomics; slots found by walking row i's columns and looking each up in R_I).  The
-// tile is written to C once, coalesced.  No device-wide atomics.
+// Numeric, owner fold (F2), general rows: a workgroup owns a tile of rows of C whose values live
+// in LDS.  Its wavefronts take the tile's fine rows I in turn, form R_I in a per-wavefront hash
+// map, and for every P(I,i) with i in the tile add P(I,i) * R_I(j) into the tile's copy of row i
+// (LDS atomics; slots found by walking row i's columns and looking each up in R_I).  The tile is
+// written to C once.  No device-wide atomics.  Tables and tiles too large for LDS live in device
+// memory (HG, TG).
 // =============================================================================================
 template <bool HG, bool TG>
 __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
                                                             const int* __restrict__ tiles,
-                                                            const int* __restrict__ tile_row0,
+                                                            TileSet ts,
                                                             const int* __restrict__ tile_fptr,
                                                             const int* __restrict__ tile_fine,
-                                                            int cap, int TE, int TR, int xcd_remap,
+                                                            int cap, int TE, int xcd_remap,
                                                             int* gtab, double* gval) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wid = threadIdx.x / WAVE, ln = lane();
@@ -566,30 +573,29 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
     b = x * q + min(x, rem) + k;
   }
   const int tile = tiles[b];
-  const int i0 = tile_row0[tile], i1 = tile_row0[tile + 1];
-  const int c0 = a.C_rowptr[i0];
-  const int ne = a.C_rowptr[i1] - c0;
+  const int tp = ts.ptr[tile], nr = ts.ptr[tile + 1] - tp;
   const Patterns& p = a.p;
 
   unsigned char* sp = smem;
   double* tv;
   const int* tc;
   int* trp = nullptr;
+  int tg_len = 0;
   if (TG) {
+    // one row longer than a tile: accumulate in C itself (zeroed beforehand)
+    const int row = ts.rows[tp];
+    const int c0 = a.C_rowptr[row];
     tv = a.C_val + c0;
     tc = a.C_col + c0;
+    tg_len = a.C_rowptr[row + 1] - c0;
   } else {
     tv = reinterpret_cast<double*>(sp);
     sp += (size_t)TE * sizeof(double);
     int* tcw = reinterpret_cast<int*>(sp);
     sp += (size_t)TE * sizeof(int);
     trp = reinterpret_cast<int*>(sp);
-    sp += (((size_t)TR + 1) * sizeof(int) + 15) / 16 * 16;
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-      tv[e] = 0.0;
-      tcw[e] = a.C_col[c0 + e];
-    }
-    for (int q = threadIdx.x; q <= i1 - i0; q += blockDim.x) trp[q] = a.C_rowptr[i0 + q] - c0;
+    sp += (((size_t)kTileRows + 1) * sizeof(int) + 15) / 16 * 16;
+    tile_load(ts.rows, tp, nr, a.C_rowptr, a.C_col, trp, tcw, tv);
     tc = tcw;
   }
   WaveScratch* ws = reinterpret_cast<WaveScratch*>(sp) + wid;
@@ -615,74 +621,78 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
   // in each); otherwise one pass over the given part.
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
-  const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
-  for (int f = tile_fptr[tile] + wid; f < f1; f += kWavesPerBlock) {
-    const int I = tile_fine[f];
-    const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
-    bool any = false;
-    for (int e = p0 + ln; e < p1; e += WAVE) {
-      const int i = p.P_col[e];
-      any |= i >= i0 && i < i1 && part_takes(part, I, i, p.n, p.m, a.K);
-    }
-    if (!ballot(any)) continue;
-    for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, a.A_val, p.P_rowptr, ws,
-                 [&](int k, double av) { hm_add<HG>(keys, vals, mask, shift, p.P_col[k], av * a.P_val[k]); });
-    if constexpr (HG) __threadfence();
-    for (int pb = p0; pb < p1; pb += WAVE) {
-      const int e = pb + ln;
-      int my_i = 0;
-      bool ok = false;
-      if (e < p1) {
-        my_i = p.P_col[e];
-        ok = my_i >= i0 && my_i < i1 && part_takes(part, I, my_i, p.n, p.m, a.K);
+    const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
+    for (int f = tile_fptr[tile] + wid; f < f1; f += kWavesPerBlock) {
+      const int I = tile_fine[f];
+      const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
+      bool any = false;
+      for (int e = p0 + ln; e < p1; e += WAVE) {
+        const int i = p.P_col[e];
+        any |= (ts.slot[i] >> kTileRowBits) == tile && part_takes(part, I, i, p.n, p.m, a.K);
       }
-      unsigned long long mk = ballot(ok);
-      const double my_w = ok ? a.P_val[e] : 0.0;
-      while (mk) {
-        const int src = __ffsll((long long)mk) - 1;
-        mk &= mk - 1;
-        const int il = __shfl(my_i, src, WAVE) - i0;
-        const double w = __shfl(my_w, src, WAVE);
-        const int cb = TG ? a.C_rowptr[i0 + il] - c0 : trp[il];
-        const int ce = TG ? a.C_rowptr[i0 + il + 1] - c0 : trp[il + 1];
-        for (int c = cb + ln; c < ce; c += WAVE) {
-          const int s = hs_find<HG>(keys, mask, shift, tc[c]);
-          if (s >= 0) {
-            if (TG)
-              unsafeAtomicAdd(tv + c, w * ld_val<HG>(vals + s));
-            else
-              atomicAdd(tv + c, w * ld_val<HG>(vals + s));
+      if (!ballot(any)) continue;
+      for_products(p.A_rowptr[I], p.A_rowptr[I + 1], p.A_col, a.A_val, p.P_rowptr, ws,
+                   [&](int k, double av) { hm_add<HG>(keys, vals, mask, shift, p.P_col[k], av * a.P_val[k]); });
+      if constexpr (HG) __threadfence();
+      for (int pb = p0; pb < p1; pb += WAVE) {
+        const int e = pb + ln;
+        int my_l = 0;
+        bool ok = false;
+        if (e < p1) {
+          const int i = p.P_col[e];
+          const int sl = ts.slot[i];
+          ok = (sl >> kTileRowBits) == tile && part_takes(part, I, i, p.n, p.m, a.K);
+          my_l = sl & (kTileRows - 1);
+        }
+        unsigned long long mk = ballot(ok);
+        const double my_w = ok ? a.P_val[e] : 0.0;
+        while (mk) {
+          const int src = __ffsll((long long)mk) - 1;
+          mk &= mk - 1;
+          const int il = __shfl(my_l, src, WAVE);
+          const double w = __shfl(my_w, src, WAVE);
+          const int cb = TG ? 0 : trp[il];
+          const int ce = TG ? tg_len : trp[il + 1];
+          for (int c = cb + ln; c < ce; c += WAVE) {
+            const int s = hs_find<HG>(keys, mask, shift, tc[c]);
+            if (s >= 0) {
+              if (TG)
+                unsafeAtomicAdd(tv + c, w * ld_val<HG>(vals + s));
+              else
+                atomicAdd(tv + c, w * ld_val<HG>(vals + s));
+            }
           }
         }
       }
+      table_clear<HG>(keys, vals, cap);
     }
-    table_clear<HG>(keys, vals, cap);
-  }
   }
   if (!TG) {
     __syncthreads();
-    for (int e = threadIdx.x; e < ne; e += blockDim.x) a.C_val[c0 + e] = tv[e];
+    tile_store(ts.rows, tp, nr, a.C_rowptr, trp, tv, a.C_val);
   }
 }
 
-hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
-                                const int* tile_fptr, const int* tile_fine, int tile_entries,
-                                int tile_rows, bool xcd_remap, int* gtab, double* gval,
-                                hipStream_t s) {
-  if (tc.count == 0) return hipSuccess;
+size_t owner_general_lds_bytes(int TE, int cap, bool hash_global, bool tile_global) {
   size_t lds = kWavesPerBlock * sizeof(WaveScratch);
-  if (!tc.tile_global)
-    lds += (size_t)tile_entries * (sizeof(double) + sizeof(int)) +
-           (((size_t)tile_rows + 1) * sizeof(int) + 15) / 16 * 16;
-  if (!tc.hash_global) lds += (size_t)kWavesPerBlock * tc.cap * (sizeof(double) + sizeof(int));
+  if (!tile_global)
+    lds += (size_t)TE * (sizeof(double) + sizeof(int)) + (((size_t)kTileRows + 1) * sizeof(int) + 15) / 16 * 16;
+  if (!hash_global) lds += (size_t)kWavesPerBlock * cap * (sizeof(double) + sizeof(int));
+  return lds;
+}
+
+hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
+                                const int* tile_fptr, const int* tile_fine, int tile_entries,
+                                bool xcd_remap, int* gtab, double* gval, hipStream_t s) {
+  if (tc.count == 0) return hipSuccess;
+  const size_t lds = owner_general_lds_bytes(tile_entries, tc.cap, tc.hash_global, tc.tile_global);
   // Spill tables are indexed by workgroup, so a spill class launches exactly its tiles and the
   // workspace holds one table per wavefront of the largest spill class.
   const int grid = tc.count;
   const int remap = xcd_remap ? 1 : 0;
 #define PTAP_LAUNCH_OWN(HG, TG)                                                                \
   hipLaunchKernelGGL((k_owner_numeric<HG, TG>), dim3(grid), dim3(kThreads), lds, s, a, tc.tiles, \
-                     tile_row0, tile_fptr, tile_fine, tc.cap, tile_entries, tile_rows, remap,    \
-                     gtab, gval)
+                     ts, tile_fptr, tile_fine, tc.cap, tile_entries, remap, gtab, gval)
   if (tc.hash_global) {
     if (tc.tile_global) PTAP_LAUNCH_OWN(true, true); else PTAP_LAUNCH_OWN(true, false);
   } else {

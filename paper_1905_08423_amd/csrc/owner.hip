@@ -1,7 +1,7 @@
 // Numeric all-at-once / merged product with the owner fold, short-row form.
 //
-// A workgroup of NW wavefronts owns a tile of contiguous rows [i0, i1) of C whose values and
-// column indices are held in LDS.  Each wavefront takes two fine rows I of the tile's list at a
+// A workgroup of NW wavefronts owns a tile of rows of C (a compact set of rows chosen at symbolic
+// time) whose values and column indices are held in LDS.  Each wavefront takes two fine rows I of the tile's list at a
 // time, one per 32-lane half:
 //   1. lane `sub` of the half loads A(I, a0+sub) and the extent of row J = A_col of P, then
 //      loads every P(J, :) entry of that row at once and inserts A(I,J) * P(J,j) into the half's
@@ -59,8 +59,8 @@ struct Stage2 {   // row extents known
 struct Stage3 {   // column of this lane's A entry and of its P entry known
   int I, J, t, pi, e;  // J = column of A(I,t) (or -1); pi = column of P(I,e) (or -1)
 };
-struct Stage4 {   // extent of row J of P known
-  int I, ps, pe, t, pi, e;
+struct Stage4 {   // extent of row J of P and the tile slot of column pi known
+  int I, ps, pe, t, pi, e, sl;
 };
 
 __device__ __forceinline__ int st_header(const int* __restrict__ fine, int fr, int f1) {
@@ -83,13 +83,15 @@ __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p)
   if (q.e >= 0) r.pi = p.P_col[q.e];
   return r;
 }
-__device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP) {
-  Stage4 r{q.I, 0, 0, q.t, q.pi, q.e};
+__device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP,
+                                          const int* __restrict__ slot) {
+  Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1};
   if (q.J >= 0) {
     const v2u pr = ld_pair(rP, q.J);
     r.ps = (int)pr[0];
     r.pe = (int)pr[1];
   }
+  if (q.pi >= 0) r.sl = slot[q.pi];
   return r;
 }
 
@@ -136,29 +138,22 @@ __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, dou
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
 // per-wavefront hash tables.  Ends with the tile written to C and a workgroup barrier.
 template <int NW>
-__device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile,
-                                                const int* __restrict__ tile_row0,
+__device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, const TileSet& ts,
                                                 const int* __restrict__ tile_fptr,
-                                                const int* __restrict__ tile_fine, int TE, int TR,
+                                                const int* __restrict__ tile_fine, int TE,
                                                 unsigned char* smem) {
   const int wid = threadIdx.x / WAVE, ln = lane();
   const int half = ln / kHalf, sub = ln % kHalf;
-  const int i0 = tile_row0[tile], i1 = tile_row0[tile + 1];
-  const int c0 = a.C_rowptr[i0];
-  const int ne = a.C_rowptr[i1] - c0;
+  const int tp = ts.ptr[tile], nr = ts.ptr[tile + 1] - tp;
   const Patterns& p = a.p;
 
   double* tv = reinterpret_cast<double*>(smem);
   int* tc = reinterpret_cast<int*>(smem + (size_t)TE * sizeof(double));
   int* trp = tc + TE;
   HalfScratch* hs = reinterpret_cast<HalfScratch*>(
-                        smem + (((size_t)TE * 12 + ((size_t)TR + 1) * 4 + 15) / 16) * 16) +
+                        smem + (((size_t)TE * 12 + ((size_t)kTileRows + 1) * 4 + 15) / 16) * 16) +
                     wid;
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    tv[e] = 0.0;
-    tc[e] = a.C_col[c0 + e];
-  }
-  for (int q = threadIdx.x; q <= i1 - i0; q += blockDim.x) trp[q] = a.C_rowptr[i0 + q] - c0;
+  tile_load(ts.rows, tp, nr, a.C_rowptr, a.C_col, trp, tc, tv);
   int* keys = hs->keys[half];
   double* vals = hs->vals[half];
   keys[sub] = EMPTY;
@@ -182,7 +177,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile,
     // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
     // load overlaps one iteration of LDS work instead of stalling the wavefront.
     const int fb = f0 + 2 * wid + half;
-    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), rA, rP, sub), p), rP);
+    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), rA, rP, sub), p), rP, ts.slot);
     Stage3 nxt = st_entries(st_rows(st_header(tile_fine, fb + step, f1), rA, rP, sub), p);
     Stage2 nn = st_rows(st_header(tile_fine, fb + 2 * step, f1), rA, rP, sub);
     for (int f = f0 + 2 * wid; f < f1; f += step) {
@@ -193,17 +188,18 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile,
       double pv[4];
       load4(rPc, rPv, p.P_col, a.P_val, cur.ps, cur.pe, nnzP, jj, pv);
       // (2) one load stage for each following pair
-      const Stage4 nxt4 = st_pext(nxt, rP);
+      const Stage4 nxt4 = st_pext(nxt, rP, ts.slot);
       const Stage3 nn3 = st_entries(nn, p);
       const Stage2 nnn2 = st_rows(st_header(tile_fine, f + 3 * step + half, f1), rA, rP, sub);
       // (3) owned entries of P(I,:) of cur, compacted per half
-      const bool in_t = cur.pi >= i0 && cur.pi < i1 && part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
+      const bool in_t = cur.sl >= 0 && (cur.sl >> kTileRowBits) == tile &&
+                        part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
       const unsigned long long bal = ballot(in_t);
       const unsigned hm = half ? (unsigned)(bal >> 32) : (unsigned)bal;
       const int nsel = __popc(hm);
       if (in_t) {
         const int pos = __popc(hm & ((1u << sub) - 1u));
-        hs->sel_i[half][pos] = cur.pi - i0;
+        hs->sel_i[half][pos] = cur.sl & (kTileRows - 1);
         hs->sel_w[half][pos] = cpw;
       }
       const int nmax = max(nsel, __shfl_xor(nsel, kHalf, WAVE));
@@ -249,16 +245,16 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile,
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) a.C_val[c0 + e] = tv[e];
+  tile_store(ts.rows, tp, nr, a.C_rowptr, trp, tv, a.C_val);
   __syncthreads();
 }
 
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
-                                                             const int* __restrict__ tile_row0,
+                                                             TileSet ts,
                                                              const int* __restrict__ tile_fptr,
                                                              const int* __restrict__ tile_fine, int TE,
-                                                             int TR, int xcd_remap) {
+                                                             int xcd_remap) {
   extern __shared__ __align__(16) unsigned char smem[];
   int b = blockIdx.x;
   if (xcd_remap) {
@@ -267,7 +263,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
     const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
     b = x * q + min(x, rem) + k;
   }
-  owner_fast_tile<NW>(a, tiles[b], tile_row0, tile_fptr, tile_fine, TE, TR, smem);
+  owner_fast_tile<NW>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
 }
 
 // Batched form: a persistent grid works through a list of (plan, tile) items, every item one tile
@@ -298,30 +294,30 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBa
       const int pk = __builtin_amdgcn_readfirstlane(w.x);
       const int tl = __builtin_amdgcn_readfirstlane(w.y);
       const OwnerBatchPlan& pl = plans[pk];
-      owner_fast_tile<NW>(pl.a, tl, pl.tile_row0, pl.tile_fptr, pl.tile_fine, pl.TE, pl.TR, smem);
+      owner_fast_tile<NW>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
     }
   }
 }
 
-size_t owner_fast_lds_bytes(int TE, int TR, int nw) {
-  return (((size_t)TE * 12 + ((size_t)TR + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
+size_t owner_fast_lds_bytes(int TE, int nw) {
+  return (((size_t)TE * 12 + ((size_t)kTileRows + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
 }
 
-hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const int* tile_row0,
-                             const int* tile_fptr, const int* tile_fine, int TE, int TR, int nw,
+hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
+                             const int* tile_fptr, const int* tile_fine, int TE, int nw,
                              bool xcd_remap, hipStream_t s) {
   if (tc.count == 0) return hipSuccess;
-  const size_t lds = owner_fast_lds_bytes(TE, TR, nw);
+  const size_t lds = owner_fast_lds_bytes(TE, nw);
   const int remap = xcd_remap ? 1 : 0;
   if (nw == 16) {
     hipLaunchKernelGGL(k_owner_fast<16>, dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
-                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+                       ts, tile_fptr, tile_fine, TE, remap);
   } else if (nw == 8) {
     hipLaunchKernelGGL(k_owner_fast<8>, dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
-                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+                       ts, tile_fptr, tile_fine, TE, remap);
   } else {
     hipLaunchKernelGGL(k_owner_fast<4>, dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
-                       tile_row0, tile_fptr, tile_fine, TE, TR, remap);
+                       ts, tile_fptr, tile_fine, TE, remap);
   }
   return hipGetLastError();
 }
