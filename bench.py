@@ -175,7 +175,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": profiled_traffic() if side == 128 else None,
-                     "kernel": "k_owner_numeric", "launch_ms_mean": round(ev_ms, 4),
+                     "kernel": "k_owner_fast (owner fold, short rows)", "launch_ms_mean": round(ev_ms, 4),
                      "launch_ms_min": round(ev_min, 4)},
         "symbolic_ms": round(sym_ms, 2),
         "rows_formed_per_numeric": st["rows_formed"],

@@ -554,7 +554,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         }
       }
       // the short-row kernel addresses P's arrays and the row pointers with 32-bit byte offsets
-      const bool fast_fits = P->nnzP * 8 < (1LL << 31) && ((long long)n + 1) * 4 < (1LL << 31);
+      const bool fast_fits = P->nnzP * 8 < (1LL << 31) && P->nnzA * 8 < (1LL << 31) &&
+                             ((long long)n + 1) * 4 < (1LL << 31);
       const bool fast_all = fast_fits && rmax_all <= kFastMaxKeys && pmax_all <= kFastMaxKeys;
       const int nw = P->opt.owner_waves ? P->opt.owner_waves : kFastWaves;
       if (nw != 4 && nw != 8 && nw != 16) fail(PTAP_ERR_INPUT);

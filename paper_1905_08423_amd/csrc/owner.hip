@@ -1,15 +1,16 @@
 // Numeric all-at-once / merged product with the owner fold, short-row form.
 //
 // A workgroup of NW wavefronts owns a tile of rows of C (a compact set of rows chosen at symbolic
-// time) whose values and column indices are held in LDS.  Each wavefront takes two fine rows I of the tile's list at a
-// time, one per 32-lane half:
-//   1. lane `sub` of the half loads A(I, a0+sub) and the extent of row J = A_col of P, then
-//      loads every P(J, :) entry of that row at once and inserts A(I,J) * P(J,j) into the half's
-//      hash map R_I (Alg. 3; compare-and-swap on the key, then an LDS FP64 add);
-//   2. the entries P(I,i) with i in the tile (and in the pass's part, Alg. 8 / Alg. 10) are
-//      compacted with a ballot;
-//   3. for each such i the half walks C's row i in LDS, looks every column up in R_I and adds
-//      P(I,i) * R_I(j) into the tile (Eq. allatonceoutproduct restricted to the owned rows).
+// time) whose values and column indices are held in LDS.  Each wavefront takes two fine rows I of
+// the tile's list at a time, one per 32-lane half:
+//   1. lane `sub` of the half holds A(I, a0+sub), the extent of row J = A_col of P and P(I, p0+sub);
+//   2. the products A(I,J) * P(J,j) of the row are dealt out 32 at a time over the half's lanes
+//      (a prefix sum of the lengths of the rows of P gives every lane its product and its row J),
+//      so consecutive lanes read consecutive entries of P, and each product is added into the
+//      half's hash map R_I (Alg. 3; compare-and-swap on the key, then an LDS FP64 add);
+//   3. for each entry P(I,i) with i in the tile (and in the pass's part, Alg. 8 / Alg. 10) the
+//      half walks C's row i in LDS, looks every column up in R_I and adds P(I,i) * R_I(j) into
+//      the tile (Eq. allatonceoutproduct restricted to the owned rows).
 // The tile is written to C once at the end.  Used when every fine row of the tile has at most
 // 32 entries in A and in P and |R_I| <= 32; other tiles take the general kernel.  Consecutive
 // row pairs of a wavefront are software-pipelined (see the loop).
@@ -23,21 +24,28 @@ constexpr int kHalf = 32;
 constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
 constexpr int kCapShift = 32 - 6;
 
+// Product walk record of one nonempty segment (one A entry of the row): its weight A(I,J) and
+// the offset that turns a product number k of the row into the index k + base of P's entry.
+struct SegRec {
+  double w;
+  int base;
+  int pad;
+};
+
 struct HalfScratch {
   int keys[2][kCap];
   double vals[2][kCap];
-  int sel_i[2][kHalf];
-  double sel_w[2][kHalf];
+  SegRec rec[2][kHalf];
 };
 }  // namespace
 
 size_t owner_fast_wave_bytes() { return sizeof(HalfScratch); }
 
-// Raw buffer resources: 32-bit byte offsets instead of 64-bit addresses, and one 8- or 16-byte
-// load per lane for a pair of row pointers or four entries of a row of P.  (Each lane reads its
-// own row of P, so the cost of a load is set by the number of distinct cache lines it touches:
-// one wide load costs about what one 4-byte load costs.)
-typedef int v4i __attribute__((ext_vector_type(4)));
+// Raw buffer resources: 32-bit byte offsets instead of 64-bit addresses, one 8-byte load for a
+// pair of row pointers, and reads past the end of an array return 0 instead of faulting.  The
+// texture address unit handles a 4-byte load at 16 lanes per cycle but an 8-byte one at 4 lanes
+// per cycle even when the lanes share an address, so values needed by a whole half-wavefront
+// (a row's index and extents) are loaded by one lane and broadcast with readlane.
 typedef unsigned v2u __attribute__((ext_vector_type(2)));
 constexpr int kRawBufferFlags = 0x00020000;  // 32-bit data format, no swizzle
 
@@ -49,90 +57,151 @@ __device__ __forceinline__ v2u ld_pair(__amdgpu_buffer_rsrc_t r, int idx) {
   return __builtin_amdgcn_raw_buffer_load_b64(r, idx * 4, 0, 0);
 }
 
+// Inclusive prefix sum (or prefix OR) over each 32-lane half of the wavefront, in VALU only:
+// DPP row shifts by 1, 2, 4, 8 scan each 16-lane row, then lane 15 of rows 0 and 2 is broadcast
+// into rows 1 and 3.  Lanes whose source lies outside the row keep the identity (old = 0).
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ int half_incl_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+  return v;
+}
+__device__ __forceinline__ int half_or_scan(int v) {
+  v |= __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+  return v;
+}
+// The value of lane 0 (half 0) or lane 32 (half 1): a value loaded once for the whole half.
+__device__ __forceinline__ int half_bcast(int v, int half) {
+  const int b0 = __builtin_amdgcn_readlane(v, 0), b1 = __builtin_amdgcn_readlane(v, 32);
+  return half ? b1 : b0;
+}
+
+__device__ __forceinline__ int ld_col(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
+}
+__device__ __forceinline__ double ld_dbl(__amdgpu_buffer_rsrc_t r, int idx) {
+  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
 // Per-lane state of one fine row at the successive stages of the pipelined loop (one row per
 // 32-lane half; lane `sub` follows the row's A entry a0+sub and P entry p0+sub).
-struct Stage2 {   // row extents known
+struct Stage2 {   // row index and extents, loaded by lanes 0 and 32 only (one per half)
   int I;          // fine row, or -1 past the end of the tile's list
-  int t;          // a0 + sub if that A entry exists, else -1
-  int e;          // p0 + sub if that P entry exists, else -1
+  int a0, a1, p0, p1;
 };
 struct Stage3 {   // column of this lane's A entry and of its P entry known
-  int I, J, t, pi, e;  // J = column of A(I,t) (or -1); pi = column of P(I,e) (or -1)
+  int I, J, t, pi, e;  // t = a0+sub, e = p0+sub (or -1); J = A_col[t], pi = P_col[e] (or -1)
 };
-struct Stage4 {   // extent of row J of P and the tile slot of column pi known
+struct Stage4 {   // extent of row J of P, the tile slot of column pi and both values known
   int I, ps, pe, t, pi, e, sl;
+  double av, pw;  // A(I,J) and P(I,pi) (0 where the entry does not exist)
 };
 
-__device__ __forceinline__ int st_header(const int* __restrict__ fine, int fr, int f1) {
-  return fr < f1 ? fine[fr] : -1;
-}
-__device__ __forceinline__ Stage2 st_rows(int I, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rP,
-                                          int sub) {
-  Stage2 r{I, -1, -1};
-  if (I >= 0) {
-    const v2u ar = ld_pair(rA, I), pr = ld_pair(rP, I);
-    const int a0 = (int)ar[0], a1 = (int)ar[1], p0 = (int)pr[0], p1 = (int)pr[1];
-    r.t = a0 + sub < a1 ? a0 + sub : -1;
-    r.e = p0 + sub < p1 ? p0 + sub : -1;
+__device__ __forceinline__ Stage2 st_rows(const int* __restrict__ fine, int fr, int f1,
+                                          __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rP, int sub) {
+  Stage2 r{-1, 0, 0, 0, 0};
+  if (sub == 0 && fr < f1) {
+    r.I = fine[fr];
+    const v2u ar = ld_pair(rA, r.I), pr = ld_pair(rP, r.I);
+    r.a0 = (int)ar[0];
+    r.a1 = (int)ar[1];
+    r.p0 = (int)pr[0];
+    r.p1 = (int)pr[1];
   }
   return r;
 }
-__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p) {
-  Stage3 r{q.I, -1, q.t, -1, q.e};
-  if (q.t >= 0) r.J = p.A_col[q.t];
-  if (q.e >= 0) r.pi = p.P_col[q.e];
+__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p, int sub, int half) {
+  const int I = half_bcast(q.I, half);
+  const int a0 = half_bcast(q.a0, half), a1 = half_bcast(q.a1, half);
+  const int p0 = half_bcast(q.p0, half), p1 = half_bcast(q.p1, half);
+  Stage3 r{I, -1, -1, -1, -1};
+  if (I >= 0) {
+    r.t = a0 + sub < a1 ? a0 + sub : -1;
+    r.e = p0 + sub < p1 ? p0 + sub : -1;
+  }
+  if (r.t >= 0) r.J = p.A_col[r.t];
+  if (r.e >= 0) r.pi = p.P_col[r.e];
   return r;
 }
 __device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP,
-                                          const int* __restrict__ slot) {
-  Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1};
+                                          const int* __restrict__ slot, __amdgpu_buffer_rsrc_t rAv,
+                                          const double* __restrict__ P_val) {
+  Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1, 0.0, 0.0};
   if (q.J >= 0) {
     const v2u pr = ld_pair(rP, q.J);
     r.ps = (int)pr[0];
     r.pe = (int)pr[1];
   }
-  if (q.pi >= 0) r.sl = slot[q.pi];
+  if (q.t >= 0) r.av = ld_dbl(rAv, q.t);
+  if (q.pi >= 0) {
+    r.sl = slot[q.pi];
+    r.pw = P_val[q.e];
+  }
   return r;
 }
 
-// Four consecutive entries k0..k0+3 of P: columns and values.  Wide loads when the whole
-// window lies inside P's arrays; otherwise entry by entry up to `ke`.
-__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t rc, __amdgpu_buffer_rsrc_t rv,
-                                      const int* __restrict__ P_col, const double* __restrict__ P_val,
-                                      int k0, int ke, int nnzP, int (&jj)[4], double (&pv)[4]) {
-  if (k0 + 4 <= nnzP) {
-    const v4i c = __builtin_amdgcn_raw_buffer_load_b128(rc, k0 * 4, 0, 0);
-    const v4i v01 = __builtin_amdgcn_raw_buffer_load_b128(rv, k0 * 8, 0, 0);
-    const v4i v23 = __builtin_amdgcn_raw_buffer_load_b128(rv, k0 * 8 + 16, 0, 0);
-    jj[0] = c[0];
-    jj[1] = c[1];
-    jj[2] = c[2];
-    jj[3] = c[3];
-    pv[0] = __hiloint2double(v01[1], v01[0]);
-    pv[1] = __hiloint2double(v01[3], v01[2]);
-    pv[2] = __hiloint2double(v23[1], v23[0]);
-    pv[3] = __hiloint2double(v23[3], v23[2]);
-  } else {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      jj[u] = 0;
-      pv[u] = 0.0;
-      if (k0 + u < ke) {
-        jj[u] = P_col[k0 + u];
-        pv[u] = P_val[k0 + u];
-      }
-    }
-  }
+// The value of lane 31 (half 0) or lane 63 (half 1): the half's total after a scan.
+__device__ __forceinline__ int half_total(int v, int half) {
+  const int t0 = __builtin_amdgcn_readlane(v, 31), t1 = __builtin_amdgcn_readlane(v, 63);
+  return half ? t1 : t0;
+}
+__device__ __forceinline__ double readlane_dbl(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
+// One step of the flattened product walk of a half: product k = 32 st + sub of the row (if it
+// exists) is entry k + base of P, weighted by A(I,J) of its segment.  `before` counts the
+// nonempty segments ending at or before the step's window and is advanced past it.
+struct ProdLoad {
+  int j;     // column of P's entry, or -1 for no product
+  double v;  // value of P's entry
+  double w;  // A(I,J)
+};
+__device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th, int sub, int half,
+                                              int& before, const SegRec* rec,
+                                              __amdgpu_buffer_rsrc_t rPc, __amdgpu_buffer_rsrc_t rPv) {
+  const int k0 = st * kHalf;
+  const int d = incl - k0 - 1;
+  const int bit = (len > 0 && (unsigned)d < (unsigned)kHalf) ? (int)(1u << d) : 0;
+  const unsigned ends = (unsigned)half_total(half_or_scan(bit), half);
+  ProdLoad r{-1, 0.0, 0.0};
+  const int k = k0 + sub;
+  if (k < Th) {
+    const int rk = (before + __popc(ends & ((1u << sub) - 1u))) & (kHalf - 1);
+    const SegRec rc = rec[rk];
+    const int e = k + rc.base;
+    r.j = ld_col(rPc, e);
+    r.v = ld_dbl(rPv, e);
+    r.w = rc.w;
+  }
+  before += __popc(ends);
+  return r;
+}
+
+// R_I(key) += v in a 64-slot LDS table.  A plain read finds keys already present (most of a
+// row's products hit a key inserted before), so only first insertions use compare-and-swap.
+// The probe is bounded by the table size (a half never holds more than 32 keys, so the bound is
+// never reached).
 __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
   unsigned s = hslot(key, kCapShift);
-  while (true) {
-    const int old = atomicCAS(keys + s, EMPTY, key);
-    if (old == EMPTY || old == key) break;
+  for (int it = 0; it < kCap; ++it) {
+    int seen = keys[s];
+    if (seen == EMPTY) seen = atomicCAS(keys + s, EMPTY, key);
+    if (seen == EMPTY || seen == key) {
+      atomicAdd(vals + s, v);
+      return;
+    }
     s = (s + 1) & (kCap - 1);
   }
-  atomicAdd(vals + s, v);
 }
 
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
@@ -169,6 +238,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   const __amdgpu_buffer_rsrc_t rP = buffer_rsrc(p.P_rowptr, (unsigned)(p.n + 1) * 4u);
   const __amdgpu_buffer_rsrc_t rPc = buffer_rsrc(p.P_col, (unsigned)nnzP * 4u);
   const __amdgpu_buffer_rsrc_t rPv = buffer_rsrc(a.P_val, (unsigned)nnzP * 8u);
+  const __amdgpu_buffer_rsrc_t rAv = buffer_rsrc(a.A_val, (unsigned)p.A_rowptr[p.n] * 8u);
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
@@ -177,62 +247,76 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
     // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
     // load overlaps one iteration of LDS work instead of stalling the wavefront.
     const int fb = f0 + 2 * wid + half;
-    Stage4 cur = st_pext(st_entries(st_rows(st_header(tile_fine, fb, f1), rA, rP, sub), p), rP, ts.slot);
-    Stage3 nxt = st_entries(st_rows(st_header(tile_fine, fb + step, f1), rA, rP, sub), p);
-    Stage2 nn = st_rows(st_header(tile_fine, fb + 2 * step, f1), rA, rP, sub);
+    Stage4 cur = st_pext(st_entries(st_rows(tile_fine, fb, f1, rA, rP, sub), p, sub, half), rP, ts.slot,
+                         rAv, a.P_val);
+    Stage3 nxt = st_entries(st_rows(tile_fine, fb + step, f1, rA, rP, sub), p, sub, half);
+    Stage2 nn = st_rows(tile_fine, fb + 2 * step, f1, rA, rP, sub);
     for (int f = f0 + 2 * wid; f < f1; f += step) {
-      // (1) values of cur's A and P entries and its first four products (the rest load in (4))
-      const double cav = cur.t >= 0 ? a.A_val[cur.t] : 0.0;
-      const double cpw = cur.e >= 0 ? a.P_val[cur.e] : 0.0;
-      int jj[4];
-      double pv[4];
-      load4(rPc, rPv, p.P_col, a.P_val, cur.ps, cur.pe, nnzP, jj, pv);
-      // (2) one load stage for each following pair
-      const Stage4 nxt4 = st_pext(nxt, rP, ts.slot);
-      const Stage3 nn3 = st_entries(nn, p);
-      const Stage2 nnn2 = st_rows(st_header(tile_fine, f + 3 * step + half, f1), rA, rP, sub);
-      // (3) owned entries of P(I,:) of cur, compacted per half
+      // (1) one load stage for each following pair
+      const Stage4 nxt4 = st_pext(nxt, rP, ts.slot, rAv, a.P_val);
+      const Stage3 nn3 = st_entries(nn, p, sub, half);
+      const Stage2 nnn2 = st_rows(tile_fine, f + 3 * step + half, f1, rA, rP, sub);
+      // (2) owned entries of P(I,:) of cur: the ones whose column is a row of this tile
       const bool in_t = cur.sl >= 0 && (cur.sl >> kTileRowBits) == tile &&
                         part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
-      const unsigned long long bal = ballot(in_t);
-      const unsigned hm = half ? (unsigned)(bal >> 32) : (unsigned)bal;
-      const int nsel = __popc(hm);
+      const unsigned long long own = ballot(in_t);
+      const unsigned own0 = (unsigned)own, own1 = (unsigned)(own >> 32);
+      // (3) the products of cur's row, 32 per step: lane q's A entry owns products
+      // [incl - len, incl) of the row; a nonempty segment of rank r leaves its weight and its
+      // offset into P in rec[r]; product k belongs to the segment of rank #{ends <= k}
+      const int len = cur.pe - cur.ps;
+      const int incl = half_incl_scan(len);
+      const int T0 = own0 ? __builtin_amdgcn_readlane(incl, 31) : 0;
+      const int T1 = own1 ? __builtin_amdgcn_readlane(incl, 63) : 0;
+      const int Th = half ? T1 : T0;
+      const unsigned long long nonempty = ballot(len > 0);
+      if (len > 0 && Th > 0) {
+        const int r = prefix_count(nonempty) - (half ? __popc((unsigned)nonempty) : 0);
+        hs->rec[half][r] = SegRec{cur.av, cur.ps - (incl - len), 0};
+      }
+      wave_sync();
+      const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
+      int before = 0;  // nonempty segments that end at or before the current window
+      // the entries of P for step st + 1 are requested before the products of step st go in
+      ProdLoad nx = prod_load(0, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
+      for (int st = 0; st < nstep; ++st) {
+        const ProdLoad cu = nx;
+        if (st + 1 < nstep) nx = prod_load(st + 1, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
+        if (cu.j >= 0) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+      }
+      wave_sync();
+      // (4) fold the owned part of P(I,:) (x) R_I into the tile, one owned entry per half at a
+      // time; its row of the tile and its weight are broadcast from the owning lane
+      int cs = 0, ce = 0;
       if (in_t) {
-        const int pos = __popc(hm & ((1u << sub) - 1u));
-        hs->sel_i[half][pos] = cur.sl & (kTileRows - 1);
-        hs->sel_w[half][pos] = cpw;
+        const int rl = cur.sl & (kTileRows - 1);
+        cs = trp[rl];
+        ce = trp[rl + 1];
       }
-      const int nmax = max(nsel, __shfl_xor(nsel, kHalf, WAVE));
-      // (4) R_I of cur in the half's hash map
-      if (nsel > 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (cur.ps + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
-        for (int k0 = cur.ps + 4; k0 < cur.pe; k0 += 4) {
-          load4(rPc, rPv, p.P_col, a.P_val, k0, cur.pe, nnzP, jj, pv);
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (k0 + u < cur.pe) hash_add64(keys, vals, jj[u], cav * pv[u]);
-        }
-      }
-      wave_sync();
-      // (6) fold the owned part of P(I,:) (x) R_I into the tile
-      for (int kk = 0; kk < nmax; ++kk) {
-        if (kk < nsel) {
-          const int rl = hs->sel_i[half][kk];
-          const double wk = hs->sel_w[half][kk];
-          const int ce = trp[rl + 1];
-          for (int c = trp[rl] + sub; c < ce; c += kHalf) {
-            const int j = tc[c];
-            unsigned s = hslot(j, kCapShift);
-            int kf;
-            while ((kf = keys[s]) != j && kf != EMPTY) s = (s + 1) & (kCap - 1);
-            if (kf == j) atomicAdd(tv + c, wk * vals[s]);
+      unsigned m0 = own0, m1 = own1;
+      while (m0 | m1) {
+        const int l0 = m0 ? __builtin_ctz(m0) : 0;
+        const int l1 = m1 ? kHalf + __builtin_ctz(m1) : kHalf;
+        const int cs0 = __builtin_amdgcn_readlane(cs, l0), ce0 = m0 ? __builtin_amdgcn_readlane(ce, l0) : cs0;
+        const int cs1 = __builtin_amdgcn_readlane(cs, l1), ce1 = m1 ? __builtin_amdgcn_readlane(ce, l1) : cs1;
+        const double w0 = readlane_dbl(cur.pw, l0), w1 = readlane_dbl(cur.pw, l1);
+        const int c1 = half ? ce1 : ce0;
+        const double wk = half ? w1 : w0;
+        for (int c = (half ? cs1 : cs0) + sub; c < c1; c += kHalf) {
+          const int j = tc[c];
+          unsigned s = hslot(j, kCapShift);
+          int kf = keys[s];
+          for (int it = 1; kf != j && kf != EMPTY && it < kCap; ++it) {
+            s = (s + 1) & (kCap - 1);
+            kf = keys[s];
           }
+          if (kf == j) atomicAdd(tv + c, wk * vals[s]);
         }
+        m0 &= m0 - 1u;
+        m1 &= m1 - 1u;
       }
       wave_sync();
-      if (nsel > 0) {
+      if (Th > 0) {
         keys[sub] = EMPTY;
         keys[sub + kHalf] = EMPTY;
         vals[sub] = 0.0;
