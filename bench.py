@@ -190,6 +190,7 @@ def main():
     if not args.headline_only:
         variants = [("allatonce_K8_owner", dict(algo="allatonce", fold="owner", nblocks=8)),
                     ("merged_K8_owner", dict(algo="merged", fold="owner", nblocks=8)),
+                    ("merged_owner_cached", dict(algo="merged", fold="owner", nblocks=1, cache=True)),
                     ("merged_atomic", dict(algo="merged", fold="atomic", nblocks=1)),
                     ("twostep", dict(algo="twostep"))]
         cmp_ms, cmp_sym = {}, {}
@@ -201,6 +202,8 @@ def main():
             out["peak_extra_mb"][name] = round(extra / 2**20, 2)
             if name == "allatonce_K8_owner":
                 out["rows_formed_allatonce_K8"] = p2.stats()["rows_formed"]
+            if name == "merged_owner_cached":
+                out["cache_mb"] = round(p2.stats()["cache_bytes"] / 2**20, 2)
             print(f"# {name}: numeric {e_ms:.3f} ms, symbolic {s_ms:.1f} ms, peak extra {extra / 2**20:.1f} MB",
                   file=sys.stderr, flush=True)
             p2.close()

@@ -94,7 +94,15 @@ typedef struct ptap_options {
   int32_t owner_waves;   /* owner fold: wavefronts per workgroup, 4, 8 or 16 (0: default 16) */
   int32_t tile_lds;      /* owner fold: LDS bytes per workgroup the tiles are sized for
                             (0: default 80 KiB, two workgroups per CU; capped by the device) */
-  int32_t reserved[6];
+  int32_t cache;         /* nonzero: cache intermediate data between numerics (Section 4.2,
+                            Table 8: repeated products keep what symbolic derived, for more
+                            memory).  Here: for every entry A(I,J) the extent of row J of P,
+                            start and length packed in 32 bits (4 * nnz(A) bytes, built at
+                            symbolic time), read by the owner fold's short-row kernel instead of
+                            looking the row pointers of P up again in every numeric.  Built only
+                            when the owner fold uses that kernel and nnz(P) < 2^26; the bytes
+                            held are reported in ptap_stats.cache_bytes. */
+  int32_t reserved[5];
 } ptap_options;
 
 typedef struct ptap_stats {
@@ -110,7 +118,8 @@ typedef struct ptap_stats {
   int32_t fold_used;           /* ptap_fold actually used */
   int32_t algo;                /* ptap_algo of the plan */
   int32_t nblocks;
-  int64_t reserved[8];
+  int64_t cache_bytes;         /* device bytes of the numeric cache (ptap_options.cache); else 0 */
+  int64_t reserved[7];
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;

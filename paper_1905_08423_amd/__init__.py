@@ -44,7 +44,8 @@ class ptap_options(ctypes.Structure):
                 ("tile_entries", ctypes.c_int32), ("hash_slots", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("backward", ctypes.c_int32), ("owner_waves", ctypes.c_int32),
-                ("tile_lds", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("tile_lds", ctypes.c_int32), ("cache", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class ptap_stats(ctypes.Structure):
@@ -54,7 +55,7 @@ class ptap_stats(ctypes.Structure):
                 ("rows_needed", ctypes.c_int64), ("fold_terms", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int32), ("fold_used", ctypes.c_int32),
                 ("algo", ctypes.c_int32), ("nblocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int64 * 8)]
+                ("cache_bytes", ctypes.c_int64), ("reserved", ctypes.c_int64 * 7)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -251,7 +252,7 @@ class Plan:
 
     def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
                  nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
-                 backward=False, owner_waves=0, tile_lds=0, allocator=None, stream=None):
+                 backward=False, owner_waves=0, tile_lds=0, cache=False, allocator=None, stream=None):
         load_library()
         self.n, self.m = int(n), int(m)
         self.A_rowptr, self.A_col = A_rowptr, A_col
@@ -269,6 +270,7 @@ class Plan:
         o.backward = 1 if backward else 0
         o.owner_waves = int(owner_waves)
         o.tile_lds = int(tile_lds)
+        o.cache = 1 if cache else 0
         self.options = o
         self.handle = None
         st, h = ptap_plan_create(self.n, self.m, A_rowptr, A_col, self.A_nnz, P_rowptr, P_col,

@@ -240,6 +240,10 @@ struct ptap_plan {
   int* gtab = nullptr;
   double* gval = nullptr;
 
+  // numeric cache (options.cache): packed extent of the row of P selected by each entry of A
+  int* A_pext = nullptr;
+  int64_t cache_bytes = 0;
+
   int fold_used = PTAP_FOLD_OWNER;
   int64_t rows_formed = 0, rows_needed = 0, fold_terms = 0;
   int64_t pattern_bytes = 0;
@@ -644,6 +648,14 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         P->tclasses.push_back(tc);
       }
       spill_need_vals = spill_need_ints;
+      // numeric cache: only the short-row kernel reads it; the start must fit in 26 bits
+      bool any_fast = false;
+      for (const auto& tc : P->tclasses) any_fast = any_fast || tc.fast;
+      if (P->opt.cache && any_fast && P->nnzP < (1LL << 26) && P->nnzA > 0) {
+        P->A_pext = t.get<int>((size_t)P->nnzA);
+        hipck(launch_pext(pat, P->nnzA, P->A_pext, s));
+        P->cache_bytes = P->nnzA * (int64_t)sizeof(int);
+      }
       t.put(P->pt_ptr);
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
@@ -724,6 +736,7 @@ static NumericArgs numeric_args(ptap_plan* P, const double* A_val, const double*
                                 double* C_val, int part) {
   NumericArgs a;
   a.p = P->pat;
+  a.A_pext = P->A_pext;
   a.A_val = A_val;
   a.P_val = P_val;
   a.C_rowptr = P->C_rowptr;
@@ -811,6 +824,7 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->fold_used = P->fold_used;
   out->algo = P->opt.algo;
   out->nblocks = P->opt.nblocks;
+  out->cache_bytes = P->cache_bytes;
   return PTAP_OK;
 }
 

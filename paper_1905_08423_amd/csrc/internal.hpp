@@ -78,6 +78,7 @@ hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_
 
 struct NumericArgs {
   Patterns p;
+  const int* A_pext;  // numeric cache, or null: per entry A(I,J), (start of P(J,:) << 6) | |P(J,:)|
   const double* A_val;
   const double* P_val;
   const int* C_rowptr;
@@ -86,6 +87,7 @@ struct NumericArgs {
   int K;
   int part;  // FoldPart
 };
+hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s);
 hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
                                  hipStream_t s);
 size_t owner_general_lds_bytes(int TE, int cap, bool hash_global, bool tile_global);

@@ -533,6 +533,25 @@ static size_t map_lds_bytes(int cap) {
   return kWavesPerBlock * (sizeof(WaveScratch) + (size_t)cap * (sizeof(int) + sizeof(double)));
 }
 
+// Numeric cache: for every entry A(I,J) the extent of row J of P, start and length packed as
+// (start << 6) | min(length, 63).  Only rows of P with at most 32 entries are read back from it
+// (the short-row owner kernel), so the length never saturates where it is used.
+__global__ void k_pext(Patterns p, long long nnzA, int* __restrict__ out) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nnzA;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int J = p.A_col[t];
+    const int ps = p.P_rowptr[J], len = p.P_rowptr[J + 1] - ps;
+    out[t] = (ps << 6) | (len < 63 ? len : 63);
+  }
+}
+
+hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s) {
+  if (nnzA == 0) return hipSuccess;
+  const long long blocks = std::min<long long>((nnzA + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_pext, dim3((unsigned)blocks), dim3(256), 0, s, p, nnzA, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
                                  hipStream_t s) {
   if (rc.count == 0) return hipSuccess;

@@ -23,6 +23,7 @@ namespace {
 constexpr int kHalf = 32;
 constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
 constexpr int kCapShift = 32 - 6;
+constexpr int kPrefetch = 3;  // product-walk steps whose loads are issued together
 
 // Product walk record of one nonempty segment (one A entry of the row): its weight A(I,J) and
 // the offset that turns a product number k of the row into the index k + base of P's entry.
@@ -97,7 +98,8 @@ struct Stage2 {   // row index and extents, loaded by lanes 0 and 32 only (one p
   int a0, a1, p0, p1;
 };
 struct Stage3 {   // column of this lane's A entry and of its P entry known
-  int I, J, t, pi, e;  // t = a0+sub, e = p0+sub (or -1); J = A_col[t], pi = P_col[e] (or -1)
+  int I, J, t, pi, e;  // t = a0+sub, e = p0+sub (or -1); J = A_col[t] (with the numeric cache:
+                       // the packed extent of row J of P), pi = P_col[e] (or -1)
 };
 struct Stage4 {   // extent of row J of P, the tile slot of column pi and both values known
   int I, ps, pe, t, pi, e, sl;
@@ -117,7 +119,9 @@ __device__ __forceinline__ Stage2 st_rows(const int* __restrict__ fine, int fr, 
   }
   return r;
 }
-__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p, int sub, int half) {
+template <bool PEXT>
+__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const NumericArgs& a, int sub, int half) {
+  const Patterns& p = a.p;
   const int I = half_bcast(q.I, half);
   const int a0 = half_bcast(q.a0, half), a1 = half_bcast(q.a1, half);
   const int p0 = half_bcast(q.p0, half), p1 = half_bcast(q.p1, half);
@@ -126,15 +130,21 @@ __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Patterns& p,
     r.t = a0 + sub < a1 ? a0 + sub : -1;
     r.e = p0 + sub < p1 ? p0 + sub : -1;
   }
-  if (r.t >= 0) r.J = p.A_col[r.t];
+  if (r.t >= 0) r.J = PEXT ? a.A_pext[r.t] : p.A_col[r.t];
   if (r.e >= 0) r.pi = p.P_col[r.e];
   return r;
 }
+template <bool PEXT>
 __device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP,
                                           const int* __restrict__ slot, __amdgpu_buffer_rsrc_t rAv,
                                           const double* __restrict__ P_val) {
   Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1, 0.0, 0.0};
-  if (q.J >= 0) {
+  if (PEXT) {
+    if (q.t >= 0) {
+      r.ps = q.J >> 6;
+      r.pe = r.ps + (q.J & 63);
+    }
+  } else if (q.J >= 0) {
     const v2u pr = ld_pair(rP, q.J);
     r.ps = (int)pr[0];
     r.pe = (int)pr[1];
@@ -206,7 +216,7 @@ __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, dou
 
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
 // per-wavefront hash tables.  Ends with the tile written to C and a workgroup barrier.
-template <int NW>
+template <int NW, bool PEXT>
 __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, const TileSet& ts,
                                                 const int* __restrict__ tile_fptr,
                                                 const int* __restrict__ tile_fine, int TE,
@@ -247,14 +257,14 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
     // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
     // load overlaps one iteration of LDS work instead of stalling the wavefront.
     const int fb = f0 + 2 * wid + half;
-    Stage4 cur = st_pext(st_entries(st_rows(tile_fine, fb, f1, rA, rP, sub), p, sub, half), rP, ts.slot,
-                         rAv, a.P_val);
-    Stage3 nxt = st_entries(st_rows(tile_fine, fb + step, f1, rA, rP, sub), p, sub, half);
+    Stage4 cur = st_pext<PEXT>(st_entries<PEXT>(st_rows(tile_fine, fb, f1, rA, rP, sub), a, sub, half), rP,
+                               ts.slot, rAv, a.P_val);
+    Stage3 nxt = st_entries<PEXT>(st_rows(tile_fine, fb + step, f1, rA, rP, sub), a, sub, half);
     Stage2 nn = st_rows(tile_fine, fb + 2 * step, f1, rA, rP, sub);
     for (int f = f0 + 2 * wid; f < f1; f += step) {
       // (1) one load stage for each following pair
-      const Stage4 nxt4 = st_pext(nxt, rP, ts.slot, rAv, a.P_val);
-      const Stage3 nn3 = st_entries(nn, p, sub, half);
+      const Stage4 nxt4 = st_pext<PEXT>(nxt, rP, ts.slot, rAv, a.P_val);
+      const Stage3 nn3 = st_entries<PEXT>(nn, a, sub, half);
       const Stage2 nnn2 = st_rows(tile_fine, f + 3 * step + half, f1, rA, rP, sub);
       // (2) owned entries of P(I,:) of cur: the ones whose column is a row of this tile
       const bool in_t = cur.sl >= 0 && (cur.sl >> kTileRowBits) == tile &&
@@ -277,11 +287,18 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
       wave_sync();
       const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
       int before = 0;  // nonempty segments that end at or before the current window
-      // the entries of P for step st + 1 are requested before the products of step st go in
-      ProdLoad nx = prod_load(0, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
-      for (int st = 0; st < nstep; ++st) {
-        const ProdLoad cu = nx;
-        if (st + 1 < nstep) nx = prod_load(st + 1, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
+      // the entries of P for the first kPrefetch steps (all of them for rows of up to 96
+      // products) are requested together, so their latencies overlap; later steps one by one
+      ProdLoad pq[kPrefetch];
+#pragma unroll
+      for (int u = 0; u < kPrefetch; ++u)
+        pq[u] = u < nstep ? prod_load(u, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv)
+                          : ProdLoad{-1, 0.0, 0.0};
+#pragma unroll
+      for (int u = 0; u < kPrefetch; ++u)
+        if (pq[u].j >= 0) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
+      for (int st = kPrefetch; st < nstep; ++st) {
+        const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
         if (cu.j >= 0) hash_add64(keys, vals, cu.j, cu.w * cu.v);
       }
       wave_sync();
@@ -333,7 +350,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   __syncthreads();
 }
 
-template <int NW>
+template <int NW, bool PEXT>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
                                                              TileSet ts,
                                                              const int* __restrict__ tile_fptr,
@@ -347,14 +364,14 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
     const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
     b = x * q + min(x, rem) + k;
   }
-  owner_fast_tile<NW>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
+  owner_fast_tile<NW, PEXT>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
 }
 
 // Batched form: a persistent grid works through a list of (plan, tile) items, every item one tile
 // of one plan's owner fold.  The list (plan by plan, tiles in order) is cut into 8 contiguous
 // chunks with a counter each; the workgroups of XCD x (workgroups are dispatched to the XCDs
 // round-robin) take items from chunk x, so neighbouring tiles share that XCD's L2, and then help
-// with the other chunks.
+// with the other chunks.  The batched form reads the row pointers of P (no numeric cache).
 template <int NW>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBatchPlan* __restrict__ plans,
                                                                    const int2* __restrict__ items,
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBa
       const int pk = __builtin_amdgcn_readfirstlane(w.x);
       const int tl = __builtin_amdgcn_readfirstlane(w.y);
       const OwnerBatchPlan& pl = plans[pk];
-      owner_fast_tile<NW>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
+      owner_fast_tile<NW, false>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
     }
   }
 }
@@ -387,22 +404,31 @@ size_t owner_fast_lds_bytes(int TE, int nw) {
   return (((size_t)TE * 12 + ((size_t)kTileRows + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
 }
 
+template <bool PEXT>
+static void launch_fast_nw(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
+                           const int* tile_fptr, const int* tile_fine, int TE, int nw, int remap,
+                           size_t lds, hipStream_t s) {
+  if (nw == 16)
+    hipLaunchKernelGGL((k_owner_fast<16, PEXT>), dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
+                       ts, tile_fptr, tile_fine, TE, remap);
+  else if (nw == 8)
+    hipLaunchKernelGGL((k_owner_fast<8, PEXT>), dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
+                       ts, tile_fptr, tile_fine, TE, remap);
+  else
+    hipLaunchKernelGGL((k_owner_fast<4, PEXT>), dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
+                       ts, tile_fptr, tile_fine, TE, remap);
+}
+
 hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
                              const int* tile_fptr, const int* tile_fine, int TE, int nw,
                              bool xcd_remap, hipStream_t s) {
   if (tc.count == 0) return hipSuccess;
   const size_t lds = owner_fast_lds_bytes(TE, nw);
   const int remap = xcd_remap ? 1 : 0;
-  if (nw == 16) {
-    hipLaunchKernelGGL(k_owner_fast<16>, dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
-  } else if (nw == 8) {
-    hipLaunchKernelGGL(k_owner_fast<8>, dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
-  } else {
-    hipLaunchKernelGGL(k_owner_fast<4>, dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
-  }
+  if (a.A_pext)
+    launch_fast_nw<true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+  else
+    launch_fast_nw<false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   return hipGetLastError();
 }
 

@@ -69,9 +69,10 @@ def test_c2_full_benchmark_configuration(c2):
                                 dict(algo="merged", fold="owner", nblocks=8),
                                 dict(algo="merged", fold="atomic"),
                                 dict(algo="allatonce", fold="atomic", nblocks=8),
-                                dict(algo="twostep")],
+                                dict(algo="twostep"),
+                                dict(algo="merged", fold="owner", cache=True)],
                          ids=["allatonce_K8_owner", "merged_K8_owner", "merged_atomic",
-                              "allatonce_K8_atomic", "twostep"])
+                              "allatonce_K8_atomic", "twostep", "merged_owner_cached"])
 def test_c2_full_other_algorithms(c2, kw):
     g, ref = c2
     _check_full(g, ref, **kw)

@@ -134,3 +134,28 @@ def test_owner_waves(waves, algo, K):
     check_against_oracle(A, P, exact=True, algo=algo, fold="owner", nblocks=K, owner_waves=waves)
     A, P = _case("c2_20")
     check_against_oracle(A, P, algo=algo, fold="owner", nblocks=K, owner_waves=waves, tile_entries=500)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2_20", "c3a_12", "c3b_9", "c3c_6", "fuzz"])
+def test_numeric_cache(case):
+    """Numeric cache (packed extents of the rows of P per entry of A, Section 4.2's caching of
+    intermediate data): same results as without it, and its size is reported."""
+    from gpu_util import GpuProblem
+    if case == "c1":
+        A, P, _ = gen.galerkin_workload("c1")
+    elif case == "fuzz":
+        A = gen.random_csr(250, 250, 0.04, seed=11, empty_rows=0.1, explicit_zeros=0.05)
+        P = gen.random_csr(250, 40, 0.08, seed=12, empty_rows=0.15, zero_cols=2, explicit_zeros=0.05)
+    else:
+        A, P = _case(case)
+    exact = case == "c1"
+    for algo, K in [("merged", 1), ("allatonce", 3)]:
+        st = check_against_oracle(A, P, exact=exact, algo=algo, fold="owner", nblocks=K, cache=True)
+        assert st["cache_bytes"] in (0, 4 * A.nnz)
+    st = check_against_oracle(A, P, exact=exact, algo="merged", fold="owner", cache=True, tile_entries=120)
+    if case in ("c1", "c2_20"):
+        assert st["cache_bytes"] == 4 * A.nnz  # every tile takes the short-row kernel here
+    g = GpuProblem(A, P)
+    plain = g.plan(algo="merged", fold="owner")
+    assert plain.stats()["cache_bytes"] == 0
+    plain.close()
