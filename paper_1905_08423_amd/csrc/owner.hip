@@ -78,22 +78,10 @@ __device__ __forceinline__ int half_or_scan(int v) {
   v |= __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
   return v;
 }
-// The value of lane 0 (half 0) or lane 32 (half 1): a value loaded once for the whole half.
-__device__ __forceinline__ int half_bcast(int v, int half) {
-  const int b0 = __builtin_amdgcn_readlane(v, 0), b1 = __builtin_amdgcn_readlane(v, 32);
-  return half ? b1 : b0;
-}
 
-__device__ __forceinline__ int ld_col(__amdgpu_buffer_rsrc_t r, int idx) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
-}
-__device__ __forceinline__ double ld_dbl(__amdgpu_buffer_rsrc_t r, int idx) {
-  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
-  return __hiloint2double((int)v[1], (int)v[0]);
-}
 // Per-lane state of one fine row at the successive stages of the pipelined loop (one row per
 // 32-lane half; lane `sub` follows the row's A entry a0+sub and P entry p0+sub).
-struct Stage2 {   // row index and extents, loaded by lanes 0 and 32 only (one per half)
+struct Stage2 {   // row index and extents (the same in every lane of a half)
   int I;          // fine row, or -1 past the end of the tile's list
   int a0, a1, p0, p1;
 };
@@ -106,10 +94,14 @@ struct Stage4 {   // extent of row J of P, the tile slot of column pi and both v
   double av, pw;  // A(I,J) and P(I,pi) (0 where the entry does not exist)
 };
 
-__device__ __forceinline__ Stage2 st_rows(const int* __restrict__ fine, int fr, int f1,
-                                          __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rP, int sub) {
+// Row headers of a wavefront's next 32 row pairs: lane h*32 + k holds the fine row of iteration
+// it0 + k of half h and that row's extents in A and P.  They are loaded together once per 32
+// iterations, so the dependent loads row index -> row pointers wait once per block instead of in
+// every iteration (a wait on a vector load also waits for every load issued before it).
+__device__ __forceinline__ Stage2 hdr_load(const int* __restrict__ fine, int fr, int f1,
+                                           __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rP) {
   Stage2 r{-1, 0, 0, 0, 0};
-  if (sub == 0 && fr < f1) {
+  if (fr < f1) {
     r.I = fine[fr];
     const v2u ar = ld_pair(rA, r.I), pr = ld_pair(rP, r.I);
     r.a0 = (int)ar[0];
@@ -119,41 +111,60 @@ __device__ __forceinline__ Stage2 st_rows(const int* __restrict__ fine, int fr, 
   }
   return r;
 }
+// The header of iteration it0 + k for this lane's half (k uniform).
+__device__ __forceinline__ Stage2 hdr_get(const Stage2& b, int k, int half) {
+  Stage2 r;
+  r.I = half ? __builtin_amdgcn_readlane(b.I, kHalf + k) : __builtin_amdgcn_readlane(b.I, k);
+  r.a0 = half ? __builtin_amdgcn_readlane(b.a0, kHalf + k) : __builtin_amdgcn_readlane(b.a0, k);
+  r.a1 = half ? __builtin_amdgcn_readlane(b.a1, kHalf + k) : __builtin_amdgcn_readlane(b.a1, k);
+  r.p0 = half ? __builtin_amdgcn_readlane(b.p0, kHalf + k) : __builtin_amdgcn_readlane(b.p0, k);
+  r.p1 = half ? __builtin_amdgcn_readlane(b.p1, kHalf + k) : __builtin_amdgcn_readlane(b.p1, k);
+  return r;
+}
+__device__ __forceinline__ int ld_col(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
+}
+__device__ __forceinline__ double ld_dbl(__amdgpu_buffer_rsrc_t r, int idx) {
+  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+
+// Buffer resources of the arrays the kernel gathers from.  Every gather below is issued
+// unconditionally: an invalid entry passes index -1, whose byte offset lies past the end of the
+// buffer, so the hardware returns 0 instead of reading; the caller masks the result.  Loads
+// without branches around them keep the compiler's wait counts exact (a wait after a branch
+// that may have issued a load has to assume it did, and vector loads complete in order).
+struct Gather {
+  __amdgpu_buffer_rsrc_t A_rowptr, P_rowptr, A_col, P_col, P_val, A_val, slot, pext;
+};
+__device__ __forceinline__ int ld_i32(__amdgpu_buffer_rsrc_t r, int idx) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
+}
+
 template <bool PEXT>
-__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const NumericArgs& a, int sub, int half) {
-  const Patterns& p = a.p;
-  const int I = half_bcast(q.I, half);
-  const int a0 = half_bcast(q.a0, half), a1 = half_bcast(q.a1, half);
-  const int p0 = half_bcast(q.p0, half), p1 = half_bcast(q.p1, half);
-  Stage3 r{I, -1, -1, -1, -1};
-  if (I >= 0) {
-    r.t = a0 + sub < a1 ? a0 + sub : -1;
-    r.e = p0 + sub < p1 ? p0 + sub : -1;
-  }
-  if (r.t >= 0) r.J = PEXT ? a.A_pext[r.t] : p.A_col[r.t];
-  if (r.e >= 0) r.pi = p.P_col[r.e];
+__device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Gather& g, int sub) {
+  Stage3 r{q.I, -1, -1, -1, -1};
+  r.t = q.I >= 0 && q.a0 + sub < q.a1 ? q.a0 + sub : -1;
+  r.e = q.I >= 0 && q.p0 + sub < q.p1 ? q.p0 + sub : -1;
+  r.J = ld_i32(PEXT ? g.pext : g.A_col, r.t);
+  r.pi = ld_i32(g.P_col, r.e);
   return r;
 }
 template <bool PEXT>
-__device__ __forceinline__ Stage4 st_pext(const Stage3& q, __amdgpu_buffer_rsrc_t rP,
-                                          const int* __restrict__ slot, __amdgpu_buffer_rsrc_t rAv,
-                                          const double* __restrict__ P_val) {
+__device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Gather& g) {
   Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1, 0.0, 0.0};
   if (PEXT) {
-    if (q.t >= 0) {
-      r.ps = q.J >> 6;
-      r.pe = r.ps + (q.J & 63);
-    }
-  } else if (q.J >= 0) {
-    const v2u pr = ld_pair(rP, q.J);
+    r.ps = q.J >> 6;  // 0 for no entry (the load returned 0)
+    r.pe = r.ps + (q.J & 63);
+  } else {
+    const v2u pr = ld_pair(g.P_rowptr, q.t >= 0 ? q.J : -1);
     r.ps = (int)pr[0];
     r.pe = (int)pr[1];
   }
-  if (q.t >= 0) r.av = ld_dbl(rAv, q.t);
-  if (q.pi >= 0) {
-    r.sl = slot[q.pi];
-    r.pw = P_val[q.e];
-  }
+  r.av = ld_dbl(g.A_val, q.t);
+  const int sl = ld_i32(g.slot, q.e >= 0 ? q.pi : -1);
+  r.sl = q.e >= 0 ? sl : -1;
+  r.pw = ld_dbl(g.P_val, q.e);
   return r;
 }
 
@@ -172,9 +183,11 @@ __device__ __forceinline__ double readlane_dbl(double v, int l) {
 // exists) is entry k + base of P, weighted by A(I,J) of its segment.  `before` counts the
 // nonempty segments ending at or before the step's window and is advanced past it.
 struct ProdLoad {
-  int j;     // column of P's entry, or -1 for no product
+  int j;     // column of P's entry (0 where there is no product)
   double v;  // value of P's entry
   double w;  // A(I,J)
+  bool ok;   // the product exists (tested only where it is inserted, so that the loads of
+             // several steps stay in flight together)
 };
 __device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th, int sub, int half,
                                               int& before, const SegRec* rec,
@@ -183,16 +196,11 @@ __device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th,
   const int d = incl - k0 - 1;
   const int bit = (len > 0 && (unsigned)d < (unsigned)kHalf) ? (int)(1u << d) : 0;
   const unsigned ends = (unsigned)half_total(half_or_scan(bit), half);
-  ProdLoad r{-1, 0.0, 0.0};
   const int k = k0 + sub;
-  if (k < Th) {
-    const int rk = (before + __popc(ends & ((1u << sub) - 1u))) & (kHalf - 1);
-    const SegRec rc = rec[rk];
-    const int e = k + rc.base;
-    r.j = ld_col(rPc, e);
-    r.v = ld_dbl(rPv, e);
-    r.w = rc.w;
-  }
+  const int rk = (before + __popc(ends & ((1u << sub) - 1u))) & (kHalf - 1);
+  const SegRec rc = rec[rk];
+  const int e = k < Th ? k + rc.base : -1;
+  ProdLoad r{ld_col(rPc, e), ld_dbl(rPv, e), rc.w, k < Th};
   before += __popc(ends);
   return r;
 }
@@ -248,30 +256,30 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   const __amdgpu_buffer_rsrc_t rP = buffer_rsrc(p.P_rowptr, (unsigned)(p.n + 1) * 4u);
   const __amdgpu_buffer_rsrc_t rPc = buffer_rsrc(p.P_col, (unsigned)nnzP * 4u);
   const __amdgpu_buffer_rsrc_t rPv = buffer_rsrc(a.P_val, (unsigned)nnzP * 8u);
-  const __amdgpu_buffer_rsrc_t rAv = buffer_rsrc(a.A_val, (unsigned)p.A_rowptr[p.n] * 8u);
+  const unsigned nnzA = (unsigned)p.A_rowptr[p.n];
+  const __amdgpu_buffer_rsrc_t rAv = buffer_rsrc(a.A_val, nnzA * 8u);
+  const Gather g{rA, rP, buffer_rsrc(p.A_col, nnzA * 4u), rPc, rPv, rAv,
+                 buffer_rsrc(ts.slot, (unsigned)p.m * 4u), buffer_rsrc(a.A_pext, PEXT ? nnzA * 4u : 0u)};
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
     // Software pipeline over the wavefront's row pairs f, f+step, f+2*step, ...: while the
-    // pair being folded (cur) works in LDS, the next pairs advance one load stage each (row
-    // index -> row extents -> entries of A and P -> extent of the row of P), so each dependent
-    // load overlaps one iteration of LDS work instead of stalling the wavefront.
+    // pair being folded (cur) works in LDS, the next two pairs advance one load stage each
+    // (entries of A and P -> extent of the row of P), so each dependent load overlaps one
+    // iteration of LDS work instead of stalling the wavefront.  Row headers come from a block
+    // loaded once per 32 iterations.
     const int fb = f0 + 2 * wid + half;
-    Stage4 cur = st_pext<PEXT>(st_entries<PEXT>(st_rows(tile_fine, fb, f1, rA, rP, sub), a, sub, half), rP,
-                               ts.slot, rAv, a.P_val);
-    Stage3 nxt = st_entries<PEXT>(st_rows(tile_fine, fb + step, f1, rA, rP, sub), a, sub, half);
-    Stage2 nn = st_rows(tile_fine, fb + 2 * step, f1, rA, rP, sub);
-    for (int f = f0 + 2 * wid; f < f1; f += step) {
-      // (1) one load stage for each following pair
-      const Stage4 nxt4 = st_pext<PEXT>(nxt, rP, ts.slot, rAv, a.P_val);
-      const Stage3 nn3 = st_entries<PEXT>(nn, a, sub, half);
-      const Stage2 nnn2 = st_rows(tile_fine, f + 3 * step + half, f1, rA, rP, sub);
-      // (2) owned entries of P(I,:) of cur: the ones whose column is a row of this tile
+    int it0 = 0;
+    Stage2 hb = hdr_load(tile_fine, fb + sub * step, f1, rA, rP);
+    Stage4 cur = st_pext<PEXT>(st_entries<PEXT>(hdr_get(hb, 0, half), g, sub), g);
+    Stage3 nxt = st_entries<PEXT>(hdr_get(hb, 1, half), g, sub);
+    for (int it = 0, f = f0 + 2 * wid; f < f1; ++it, f += step) {
+      // (1) owned entries of P(I,:) of cur: the ones whose column is a row of this tile
       const bool in_t = cur.sl >= 0 && (cur.sl >> kTileRowBits) == tile &&
                         part_takes(part, cur.I, cur.pi, p.n, p.m, a.K);
       const unsigned long long own = ballot(in_t);
       const unsigned own0 = (unsigned)own, own1 = (unsigned)(own >> 32);
-      // (3) the products of cur's row, 32 per step: lane q's A entry owns products
+      // (2) the products of cur's row, 32 per step: lane q's A entry owns products
       // [incl - len, incl) of the row; a nonempty segment of rank r leaves its weight and its
       // offset into P in rec[r]; product k belongs to the segment of rank #{ends <= k}
       const int len = cur.pe - cur.ps;
@@ -293,15 +301,27 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
 #pragma unroll
       for (int u = 0; u < kPrefetch; ++u)
         pq[u] = u < nstep ? prod_load(u, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv)
-                          : ProdLoad{-1, 0.0, 0.0};
+                          : ProdLoad{0, 0.0, 0.0, false};
 #pragma unroll
       for (int u = 0; u < kPrefetch; ++u)
-        if (pq[u].j >= 0) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
+        if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
       for (int st = kPrefetch; st < nstep; ++st) {
         const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
-        if (cu.j >= 0) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+        if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v);
       }
       wave_sync();
+      // (3) one load stage for each of the next two pairs.  Issued after the products' loads
+      // have been consumed (a wait on a vector load also waits for all loads issued before it),
+      // these fly during the fold, which works in LDS only.
+      int k = it + 2 - it0;
+      if (k == kHalf) {
+        it0 += kHalf;
+        k = 0;
+        hb = hdr_load(tile_fine, fb + (it0 + sub) * step, f1, rA, rP);
+      }
+      const Stage2 h2 = hdr_get(hb, k, half);
+      const Stage4 nxt4 = st_pext<PEXT>(nxt, g);
+      const Stage3 nn3 = st_entries<PEXT>(h2, g, sub);
       // (4) fold the owned part of P(I,:) (x) R_I into the tile, one owned entry per half at a
       // time; its row of the tile and its weight are broadcast from the owning lane
       int cs = 0, ce = 0;
@@ -342,7 +362,6 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
       wave_sync();
       cur = nxt4;
       nxt = nn3;
-      nn = nnn2;
     }
   }
   __syncthreads();
