@@ -25,8 +25,10 @@ constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
 constexpr int kCapShift = 32 - 6;
 constexpr int kPrefetch = 3;  // product-walk steps whose loads are issued together
 
-// Product walk record of one nonempty segment (one A entry of the row): its weight A(I,J) and
-// the offset that turns a product number k of the row into the index k + base of P's entry.
+// Record of one nonempty segment of the product walk (one A entry of the row): its weight
+// A(I,J) and the offset that turns a product number k of the row into the index k + base of
+// P's entry.  The fold reuses the records for the owned entries: weight P(I,i), and the start
+// (base) and end (pad) of row i of the tile.
 struct SegRec {
   double w;
   int base;
@@ -173,11 +175,6 @@ __device__ __forceinline__ int half_total(int v, int half) {
   const int t0 = __builtin_amdgcn_readlane(v, 31), t1 = __builtin_amdgcn_readlane(v, 63);
   return half ? t1 : t0;
 }
-__device__ __forceinline__ double readlane_dbl(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
 
 // One step of the flattened product walk of a half: product k = 32 st + sub of the row (if it
 // exists) is entry k + base of P, weighted by A(I,J) of its segment.  `before` counts the
@@ -323,34 +320,33 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
       const Stage4 nxt4 = st_pext<PEXT>(nxt, g);
       const Stage3 nn3 = st_entries<PEXT>(h2, g, sub);
       // (4) fold the owned part of P(I,:) (x) R_I into the tile, one owned entry per half at a
-      // time; its row of the tile and its weight are broadcast from the owning lane
-      int cs = 0, ce = 0;
-      if (in_t) {
-        const int rl = cur.sl & (kTileRows - 1);
-        cs = trp[rl];
-        ce = trp[rl + 1];
-      }
-      unsigned m0 = own0, m1 = own1;
-      while (m0 | m1) {
-        const int l0 = m0 ? __builtin_ctz(m0) : 0;
-        const int l1 = m1 ? kHalf + __builtin_ctz(m1) : kHalf;
-        const int cs0 = __builtin_amdgcn_readlane(cs, l0), ce0 = m0 ? __builtin_amdgcn_readlane(ce, l0) : cs0;
-        const int cs1 = __builtin_amdgcn_readlane(cs, l1), ce1 = m1 ? __builtin_amdgcn_readlane(ce, l1) : cs1;
-        const double w0 = readlane_dbl(cur.pw, l0), w1 = readlane_dbl(cur.pw, l1);
-        const int c1 = half ? ce1 : ce0;
-        const double wk = half ? w1 : w0;
-        for (int c = (half ? cs1 : cs0) + sub; c < c1; c += kHalf) {
-          const int j = tc[c];
-          unsigned s = hslot(j, kCapShift);
-          int kf = keys[s];
-          for (int it = 1; kf != j && kf != EMPTY && it < kCap; ++it) {
-            s = (s + 1) & (kCap - 1);
-            kf = keys[s];
-          }
-          if (kf == j) atomicAdd(tv + c, wk * vals[s]);
+      // time.  The owned entries leave (row start, row end, weight) in the half's records (free
+      // once the products are in), compacted by rank, and every lane reads them back with one
+      // broadcast LDS read per entry.
+      {
+        const unsigned hm = half ? own1 : own0;
+        if (in_t) {
+          const int rl = cur.sl & (kTileRows - 1);
+          const int pos = __popc(hm & ((1u << sub) - 1u));
+          hs->rec[half][pos] = SegRec{cur.pw, trp[rl], trp[rl + 1]};
         }
-        m0 &= m0 - 1u;
-        m1 &= m1 - 1u;
+        wave_sync();
+        const int nsel = __popc(hm);
+        const int nmax = max(__popc(own0), __popc(own1));
+        for (int kk = 0; kk < nmax; ++kk) {
+          const SegRec rc = hs->rec[half][kk];
+          const int c0 = kk < nsel ? rc.base : 0, c1 = kk < nsel ? rc.pad : 0;
+          for (int c = c0 + sub; c < c1; c += kHalf) {
+            const int j = tc[c];
+            unsigned s = hslot(j, kCapShift);
+            int kf = keys[s];
+            for (int it = 1; kf != j && kf != EMPTY && it < kCap; ++it) {
+              s = (s + 1) & (kCap - 1);
+              kf = keys[s];
+            }
+            if (kf == j) atomicAdd(tv + c, rc.w * vals[s]);
+          }
+        }
       }
       wave_sync();
       if (Th > 0) {
