@@ -113,14 +113,17 @@ __device__ __forceinline__ Stage2 hdr_load(const int* __restrict__ fine, int fr,
   }
   return r;
 }
-// The header of iteration it0 + k for this lane's half (k uniform).
+// The header of iteration it0 + k for this lane's half (k uniform): a backward permute from
+// lane half*32 + k (one LDS-crossbar operation per value instead of two readlanes and a select).
+// Every lane of the wavefront must be active.
 __device__ __forceinline__ Stage2 hdr_get(const Stage2& b, int k, int half) {
+  const int src = (half * kHalf + k) * 4;
   Stage2 r;
-  r.I = half ? __builtin_amdgcn_readlane(b.I, kHalf + k) : __builtin_amdgcn_readlane(b.I, k);
-  r.a0 = half ? __builtin_amdgcn_readlane(b.a0, kHalf + k) : __builtin_amdgcn_readlane(b.a0, k);
-  r.a1 = half ? __builtin_amdgcn_readlane(b.a1, kHalf + k) : __builtin_amdgcn_readlane(b.a1, k);
-  r.p0 = half ? __builtin_amdgcn_readlane(b.p0, kHalf + k) : __builtin_amdgcn_readlane(b.p0, k);
-  r.p1 = half ? __builtin_amdgcn_readlane(b.p1, kHalf + k) : __builtin_amdgcn_readlane(b.p1, k);
+  r.I = __builtin_amdgcn_ds_bpermute(src, b.I);
+  r.a0 = __builtin_amdgcn_ds_bpermute(src, b.a0);
+  r.a1 = __builtin_amdgcn_ds_bpermute(src, b.a1);
+  r.p0 = __builtin_amdgcn_ds_bpermute(src, b.p0);
+  r.p1 = __builtin_amdgcn_ds_bpermute(src, b.p1);
   return r;
 }
 __device__ __forceinline__ int ld_col(__amdgpu_buffer_rsrc_t r, int idx) {
@@ -208,6 +211,7 @@ __device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th,
 // never reached).
 __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
   unsigned s = hslot(key, kCapShift);
+#pragma unroll 1  // rarely more than one probe: unrolling only adds exec-mask bookkeeping
   for (int it = 0; it < kCap; ++it) {
     int seen = keys[s];
     if (seen == EMPTY) seen = atomicCAS(keys + s, EMPTY, key);
@@ -340,6 +344,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
             const int j = tc[c];
             unsigned s = hslot(j, kCapShift);
             int kf = keys[s];
+#pragma unroll 1
             for (int it = 1; kf != j && kf != EMPTY && it < kCap; ++it) {
               s = (s + 1) & (kCap - 1);
               kf = keys[s];
