@@ -23,7 +23,7 @@ namespace {
 constexpr int kHalf = 32;
 constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
 constexpr int kCapShift = 32 - 6;
-constexpr int kPrefetch = 3;  // product-walk steps whose loads are issued together
+constexpr int kPrefetch = 4;  // product-walk steps whose loads are issued together
 
 // Record of one nonempty segment of the product walk (one A entry of the row): its weight
 // A(I,J) and the offset that turns a product number k of the row into the index k + base of
@@ -296,7 +296,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
       wave_sync();
       const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
       int before = 0;  // nonempty segments that end at or before the current window
-      // the entries of P for the first kPrefetch steps (all of them for rows of up to 96
+      // the entries of P for the first kPrefetch steps (all of them for rows of up to 128
       // products) are requested together, so their latencies overlap; later steps one by one
       ProdLoad pq[kPrefetch];
 #pragma unroll
