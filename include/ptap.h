@@ -119,7 +119,8 @@ typedef struct ptap_stats {
   int32_t algo;                /* ptap_algo of the plan */
   int32_t nblocks;
   int64_t cache_bytes;         /* device bytes of the numeric cache (ptap_options.cache); else 0 */
-  int64_t reserved[7];
+  int64_t block_size;          /* bs of a block-sparse plan (ptap_plan_create_bsr); else 1 */
+  int64_t reserved[6];
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;
@@ -141,6 +142,25 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
                              const int32_t* A_col, int64_t A_nnz, const int32_t* P_rowptr,
                              const int32_t* P_col, int64_t P_nnz, const ptap_options* opts,
                              const ptap_allocator* alloc, hipStream_t stream);
+
+/*
+ * Block-sparse (BSR) plan: A (nb x nb blocks) and P (nb x mb blocks) hold dense bs x bs blocks
+ * on the given block patterns, for systems with bs coupled unknowns per node (Section 4.2's
+ * neutron-transport problem has many variables per vertex).  The triple product is the same,
+ * C(i,j) = sum_{I,J} P(I,i)^T A(I,J) P(J,j) block by block; C comes back as blocks on the block
+ * pattern that ptap_get_pattern returns (mb + 1 row pointers, nnz(C) block columns).  Values
+ * passed to ptap_numeric are nnz blocks of bs*bs doubles each, row-major, in pattern order (A:
+ * A_nnzb blocks, P: P_nnzb blocks, C: nnz(C) blocks).  The numeric phase uses the row form of
+ * the all-at-once product (Eq. allatoncerow), one workgroup per block row of C accumulating in
+ * LDS; rows too long for LDS add into C with device atomics.  1 <= bs <= 8.  Options: algo must
+ * not be two-step; fold and cache are ignored; backward is not supported; ptap_backward and
+ * ptap_batch_create reject block plans.  Errors: as ptap_plan_create, plus PTAP_ERR_UNSUPPORTED.
+ */
+ptap_status ptap_plan_create_bsr(ptap_plan** out, int32_t nb, int32_t mb, int32_t bs,
+                                 const int32_t* A_rowptr, const int32_t* A_col, int64_t A_nnzb,
+                                 const int32_t* P_rowptr, const int32_t* P_col, int64_t P_nnzb,
+                                 const ptap_options* opts, const ptap_allocator* alloc,
+                                 hipStream_t stream);
 
 /*
  * Symbolic phase (Section 2; Alg. 7/9 for all-at-once and merged, Alg. 5 for two-step):

@@ -55,7 +55,8 @@ class ptap_stats(ctypes.Structure):
                 ("rows_needed", ctypes.c_int64), ("fold_terms", ctypes.c_int64),
                 ("n_tiles", ctypes.c_int32), ("fold_used", ctypes.c_int32),
                 ("algo", ctypes.c_int32), ("nblocks", ctypes.c_int32),
-                ("cache_bytes", ctypes.c_int64), ("reserved", ctypes.c_int64 * 7)]
+                ("cache_bytes", ctypes.c_int64), ("block_size", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 6)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -68,6 +69,9 @@ _SIGNATURES = {
     "ptap_options_default": (None, [ctypes.POINTER(ptap_options)]),
     "ptap_plan_create": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, _vp, _vp, _i64, _vp, _vp, _i64,
                                         ctypes.POINTER(ptap_options), ctypes.POINTER(ptap_allocator), _vp]),
+    "ptap_plan_create_bsr": (ctypes.c_int, [ctypes.POINTER(_vp), _i32, _i32, _i32, _vp, _vp, _i64, _vp, _vp,
+                                            _i64, ctypes.POINTER(ptap_options), ctypes.POINTER(ptap_allocator),
+                                            _vp]),
     "ptap_symbolic": (ctypes.c_int, [_vp, _vp]),
     "ptap_get_pattern": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ptap_numeric": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -151,6 +155,17 @@ def ptap_plan_create(n, m, A_rowptr, A_col, A_nnz, P_rowptr, P_col, P_nnz, opts=
                                          ctypes.byref(opts) if opts is not None else None,
                                          ctypes.byref(alloc) if alloc is not None else None,
                                          _stream(stream))
+    return st, h
+
+
+def ptap_plan_create_bsr(nb, mb, bs, A_rowptr, A_col, A_nnzb, P_rowptr, P_col, P_nnzb, opts=None,
+                         alloc=None, stream=None):
+    h = ctypes.c_void_p()
+    st = load_library().ptap_plan_create_bsr(ctypes.byref(h), nb, mb, bs, _ptr(A_rowptr), _ptr(A_col),
+                                             A_nnzb, _ptr(P_rowptr), _ptr(P_col), P_nnzb,
+                                             ctypes.byref(opts) if opts is not None else None,
+                                             ctypes.byref(alloc) if alloc is not None else None,
+                                             _stream(stream))
     return st, h
 
 
@@ -248,11 +263,14 @@ class Plan:
     """A plan for C = P^T A P on fixed patterns of A and P (device tensors).
 
     algo: "allatonce" | "merged" | "twostep"; fold: "auto" | "atomic" | "owner"; nblocks: K.
+    block_size > 1 makes a block-sparse plan (ptap_plan_create_bsr): n, m and the patterns count
+    blocks, and values are blocks of block_size^2 doubles (row-major).
     The symbolic phase runs at construction; numeric() may be called many times."""
 
     def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
                  nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
-                 backward=False, owner_waves=0, tile_lds=0, cache=False, allocator=None, stream=None):
+                 backward=False, owner_waves=0, tile_lds=0, cache=False, block_size=1, allocator=None,
+                 stream=None):
         load_library()
         self.n, self.m = int(n), int(m)
         self.A_rowptr, self.A_col = A_rowptr, A_col
@@ -273,9 +291,15 @@ class Plan:
         o.cache = 1 if cache else 0
         self.options = o
         self.handle = None
-        st, h = ptap_plan_create(self.n, self.m, A_rowptr, A_col, self.A_nnz, P_rowptr, P_col,
-                                 self.P_nnz, o, self.allocator.struct, stream)
-        _check(st, "ptap_plan_create")
+        self.bs = int(block_size)
+        if self.bs == 1:
+            st, h = ptap_plan_create(self.n, self.m, A_rowptr, A_col, self.A_nnz, P_rowptr, P_col,
+                                     self.P_nnz, o, self.allocator.struct, stream)
+            _check(st, "ptap_plan_create")
+        else:
+            st, h = ptap_plan_create_bsr(self.n, self.m, self.bs, A_rowptr, A_col, self.A_nnz, P_rowptr,
+                                         P_col, self.P_nnz, o, self.allocator.struct, stream)
+            _check(st, "ptap_plan_create_bsr")
         self.handle = h
         _check(ptap_symbolic(self.handle, stream), "ptap_symbolic")
         st, nnz, rp, col = ptap_get_pattern(self.handle)
@@ -302,8 +326,13 @@ class Plan:
         return rp, col
 
     def numeric(self, A_val, P_val, C_val=None, stream=None):
+        b2 = self.bs * self.bs
+        if A_val.numel() != self.A_nnz * b2 or P_val.numel() != self.P_nnz * b2:
+            raise ValueError("A_val / P_val do not match the patterns and the block size")
         if C_val is None:
-            C_val = torch.empty(self.nnz_C, dtype=torch.float64, device=A_val.device)
+            C_val = torch.empty(self.nnz_C * b2, dtype=torch.float64, device=A_val.device)
+        elif C_val.numel() != self.nnz_C * b2:
+            raise ValueError("C_val does not match the pattern of C and the block size")
         _check(ptap_numeric(self.handle, A_val, P_val, C_val, stream), "ptap_numeric")
         return C_val
 

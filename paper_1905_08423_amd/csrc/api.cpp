@@ -244,6 +244,12 @@ struct ptap_plan {
   int* A_pext = nullptr;
   int64_t cache_bytes = 0;
 
+  // block-sparse plans (ptap_plan_create_bsr): block size, rows of C accumulated in LDS or in C
+  int bs = 1;
+  int* bsr_rows_lds = nullptr;
+  int* bsr_rows_glob = nullptr;
+  int bsr_n_lds = 0, bsr_n_glob = 0, bsr_cap = 64, bsr_ncmax = 0;
+
   int fold_used = PTAP_FOLD_OWNER;
   int64_t rows_formed = 0, rows_needed = 0, fold_terms = 0;
   int64_t pattern_bytes = 0;
@@ -349,6 +355,28 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
   return PTAP_OK;
 }
 
+ptap_status ptap_plan_create_bsr(ptap_plan** out, int32_t nb, int32_t mb, int32_t bs,
+                                 const int32_t* A_rowptr, const int32_t* A_col, int64_t A_nnzb,
+                                 const int32_t* P_rowptr, const int32_t* P_col, int64_t P_nnzb,
+                                 const ptap_options* opts, const ptap_allocator* alloc,
+                                 hipStream_t stream) {
+  if (!out) return PTAP_ERR_INPUT;
+  *out = nullptr;
+  if (bs < 1 || bs > kBsrMaxBlock) return PTAP_ERR_INPUT;
+  ptap_options o;
+  ptap_options_default(&o);
+  if (opts) o = *opts;
+  if (o.algo == PTAP_TWOSTEP || o.backward) return PTAP_ERR_UNSUPPORTED;
+  if ((A_nnzb + 1) * bs * bs > (int64_t)1 << 40 || (P_nnzb + 1) * bs * bs > (int64_t)1 << 40)
+    return PTAP_ERR_TOO_LARGE;
+  o.fold = PTAP_FOLD_OWNER;
+  o.cache = 0;
+  ptap_status st = ptap_plan_create(out, nb, mb, A_rowptr, A_col, A_nnzb, P_rowptr, P_col, P_nnzb, &o,
+                                    alloc, stream);
+  if (st == PTAP_OK) (*out)->bs = bs;
+  return st;
+}
+
 static void validate_patterns(ptap_plan* P, hipStream_t s) {
   const Patterns& pat = P->pat;
   int* err = P->mem.get<int>(1);
@@ -367,6 +395,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   const Patterns& pat = P->pat;
   const int n = pat.n, m = pat.m;
   const bool two = P->opt.algo == PTAP_TWOSTEP;
+  const bool blk = P->bs > 1;
   // The patterns are caller-owned; with validation on they are checked again right before use,
   // so that arrays changed or released since plan creation are reported instead of read.
   if (P->opt.validate) validate_patterns(P, s);
@@ -375,7 +404,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   std::vector<int> h_pt_ptr(m + 1, 0);
   P->pt_ptr = t.get<int>(m + 1);
   P->pt_row = t.get<int>(P->nnzP);
-  P->pt_pos = two ? t.get<int>(P->nnzP) : nullptr;
+  P->pt_pos = (two || blk) ? t.get<int>(P->nnzP) : nullptr;
   {
     int* cnt = t.get<int>(m + 1);
     hipck(launch_fill_i32(cnt, 0, m + 1, s));
@@ -498,7 +527,38 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   size_t spill_need_ints = 0, spill_need_vals = 0;
   const int lmax = P->lds_hash_max;
 
-  if (two) {
+  if (blk) {
+    // Block rows: the row form, one workgroup per row of C (bsr.hip).  Rows whose accumulators
+    // fit the LDS target are summed in LDS; longer rows add into C with device atomics.
+    P->fold_used = PTAP_FOLD_OWNER;
+    P->rows_formed = P->nnzP;  // a fine block row is formed once per block of its row of P
+    const size_t target = std::min<size_t>((size_t)P->lds_device, 65536);
+    int ncmax = 0;
+    std::vector<int> lrows, grows;
+    for (int i = 0; i < m; ++i) {
+      const int nc = h_c_ptr[i + 1] - h_c_ptr[i];
+      if (nc == 0) continue;
+      if (bsr_lds_bytes(P->bs, cap_for(nc), nc, true) <= target) {
+        lrows.push_back(i);
+        ncmax = std::max(ncmax, nc);
+      } else {
+        grows.push_back(i);
+      }
+    }
+    P->bsr_ncmax = ncmax;
+    P->bsr_cap = cap_for(std::max(ncmax, 1));
+    if (bsr_lds_bytes(P->bs, P->bsr_cap, ncmax, true) > (size_t)P->lds_device) fail(PTAP_ERR_UNSUPPORTED);
+    P->bsr_n_lds = (int)lrows.size();
+    P->bsr_n_glob = (int)grows.size();
+    if (!lrows.empty()) {
+      P->bsr_rows_lds = t.get<int>(lrows.size());
+      to_device(P->bsr_rows_lds, lrows, s);
+    }
+    if (!grows.empty()) {
+      P->bsr_rows_glob = t.get<int>(grows.size());
+      to_device(P->bsr_rows_glob, grows, s);
+    }
+  } else if (two) {
     P->fold_used = PTAP_FOLD_AUTO;
     P->AP_val = t.get<double>(P->nnzAP);
     P->PT_val = t.get<double>(P->nnzP);
@@ -754,6 +814,16 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
   if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!C_val && P->nnzC)) return PTAP_ERR_INPUT;
   try {
     if (P->nnzC == 0) return PTAP_OK;
+    if (P->bs > 1) {
+      const BsrArgs b{P->pat.A_rowptr, P->pat.A_col, P->pat.P_rowptr, P->pat.P_col, A_val, P_val,
+                      P->C_rowptr, P->C_col, C_val, P->pt_ptr, P->pt_row, P->pt_pos};
+      if (P->bsr_n_glob) hipck(launch_fill_f64(C_val, 0.0, P->nnzC * P->bs * P->bs, s));
+      hipck(launch_bsr_numeric(b, P->bs, P->bsr_rows_lds, P->bsr_n_lds, P->bsr_cap, P->bsr_ncmax, true,
+                               P->opt.xcd_remap != 0, s));
+      hipck(launch_bsr_numeric(b, P->bs, P->bsr_rows_glob, P->bsr_n_glob, 64, 0, false,
+                               P->opt.xcd_remap != 0, s));
+      return PTAP_OK;
+    }
     if (P->opt.algo == PTAP_TWOSTEP) {
       NumericArgs a = numeric_args(P, A_val, P_val, C_val, PART_ALL);
       for (auto& c : P->ap_rows)
@@ -794,6 +864,7 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
 ptap_status ptap_backward(ptap_plan* P, const double* A_val, const double* P_val,
                           const double* dC_val, double* dA_val, double* dP_val, hipStream_t s) {
   if (!P) return PTAP_ERR_INPUT;
+  if (P->bs > 1) return PTAP_ERR_UNSUPPORTED;
   if (!P->sym_done) return PTAP_ERR_STATE;
   if (!P->opt.backward) return PTAP_ERR_STATE;
   if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!dC_val && P->nnzC)) return PTAP_ERR_INPUT;
@@ -825,6 +896,7 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->algo = P->opt.algo;
   out->nblocks = P->opt.nblocks;
   out->cache_bytes = P->cache_bytes;
+  out->block_size = P->bs;
   return PTAP_OK;
 }
 
@@ -842,6 +914,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
   if (alloc && (!alloc->alloc || !alloc->release)) return PTAP_ERR_INPUT;
   for (int k = 0; k < count; ++k) {
     if (!plans[k]) return PTAP_ERR_INPUT;
+    if (plans[k]->bs > 1) return PTAP_ERR_UNSUPPORTED;
     if (!plans[k]->sym_done) return PTAP_ERR_STATE;
     if (plans[k]->opt.algo == PTAP_TWOSTEP || plans[k]->fold_used != PTAP_FOLD_OWNER)
       return PTAP_ERR_UNSUPPORTED;

@@ -88,6 +88,26 @@ struct NumericArgs {
   int part;  // FoldPart
 };
 hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s);
+
+// Block-sparse (BSR) numeric in the row form: one workgroup per row of C (bsr.hip).
+struct BsrArgs {
+  const int* A_rowptr;
+  const int* A_col;
+  const int* P_rowptr;
+  const int* P_col;
+  const double* A_val;  // nnz(A) blocks of bs*bs, row-major
+  const double* P_val;
+  const int* C_rowptr;
+  const int* C_col;
+  double* C_val;
+  const int* pt_ptr;  // column lists of P: fine rows and positions of the blocks P(I,i)
+  const int* pt_row;
+  const int* pt_pos;
+};
+constexpr int kBsrMaxBlock = 8;
+size_t bsr_lds_bytes(int bs, int cap, int ncmax, bool lds_acc);
+hipError_t launch_bsr_numeric(const BsrArgs& a, int bs, const int* rows, int nrows, int cap, int ncmax,
+                              bool lds_acc, bool remap, hipStream_t s);
 hipError_t launch_atomic_numeric(const NumericArgs& a, const RowClass& rc, int* gtab, double* gval,
                                  hipStream_t s);
 size_t owner_general_lds_bytes(int TE, int cap, bool hash_global, bool tile_global);

@@ -27,7 +27,8 @@ __all__ = [
     "CSR", "laplacian7", "stencil27", "trilinear_1d", "trilinear", "coarse_side",
     "smoothed_aggregation", "block_stencil27", "block_smoothed_aggregation",
     "random_csr", "toy_rowwise", "galerkin_workload", "batch_problem_sides",
-    "hierarchy_sides", "loss_weights", "to_scipy", "from_scipy",
+    "hierarchy_sides", "loss_weights", "to_scipy", "from_scipy", "BSR", "csr_to_bsr", "bsr_to_csr",
+    "random_bsr",
 ]
 
 
@@ -315,6 +316,77 @@ def block_smoothed_aggregation(A: CSR, nx: int, G: int, *, agg: int = 3, steps: 
     P = sp.csr_matrix(P)
     P.eliminate_zeros()
     return from_scipy(P)
+
+
+# --------------------------------------------------------------------------------------------
+# Block-sparse (BSR) layout: dense bs x bs blocks on a block pattern
+# --------------------------------------------------------------------------------------------
+
+@dataclass
+class BSR:
+    """Block CSR: nb x mb blocks of bs x bs; val[k] is block k, row-major (nnzb x bs x bs)."""
+
+    nb: int
+    mb: int
+    bs: int
+    rowptr: np.ndarray  # int32 [nb + 1]
+    col: np.ndarray     # int32 [nnzb], sorted and unique within each block row
+    val: np.ndarray     # float64 [nnzb, bs, bs]
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.rowptr[-1])
+
+
+def csr_to_bsr(M: CSR, bs: int) -> BSR:
+    """The block layout of a scalar CSR matrix whose stored entries fill whole bs x bs blocks
+    (row = node*bs + g).  In such a matrix the bs scalar rows of block row bi hold the same
+    block columns, bs consecutive entries per block.  Raises ValueError otherwise."""
+    if M.n_rows % bs or M.n_cols % bs:
+        raise ValueError("shape is not a multiple of the block size")
+    nb, mb = M.n_rows // bs, M.n_cols // bs
+    rp = M.rowptr.astype(np.int64)
+    lens = np.diff(rp).reshape(nb, bs)
+    if np.any(lens % bs) or np.any(lens != lens[:, :1]):
+        raise ValueError("a block of the pattern is not complete")
+    nblk = lens[:, 0] // bs
+    browptr = np.concatenate([[0], np.cumsum(nblk)]).astype(np.int64)
+    nnzb = int(browptr[-1])
+    bi = np.repeat(np.arange(nb), nblk)
+    q = np.arange(nnzb) - browptr[bi]
+    g = np.arange(bs)
+    # start of block k's row g in the scalar arrays, then its bs consecutive entries
+    base = rp[bi[:, None] * bs + g[None, :]] + q[:, None] * bs
+    idx = base[:, :, None] + g[None, None, :]
+    cols = M.col[idx]
+    bcol = cols[:, 0, 0] // bs
+    if np.any(cols != bcol[:, None, None] * bs + g[None, None, :]):
+        raise ValueError("a block of the pattern is not complete")
+    return BSR(nb, mb, bs, browptr.astype(np.int32), bcol.astype(np.int32),
+               np.ascontiguousarray(M.val[idx], dtype=np.float64))
+
+
+def bsr_to_csr(B: BSR) -> CSR:
+    """Scalar CSR expansion of a BSR matrix (every entry of every stored block is stored)."""
+    bs = B.bs
+    brow = np.repeat(np.arange(B.nb), np.diff(B.rowptr))
+    g = np.arange(bs)
+    rows = (brow[:, None, None] * bs + g[None, :, None]).repeat(bs, axis=2)
+    cols = (B.col[:, None, None].astype(np.int64) * bs + g[None, None, :]).repeat(bs, axis=1)
+    order = np.lexsort((cols.ravel(), rows.ravel()))
+    r, c, v = rows.ravel()[order], cols.ravel()[order], B.val.reshape(-1)[order]
+    rowptr = np.zeros(B.nb * bs + 1, dtype=np.int64)
+    np.add.at(rowptr, r + 1, 1)
+    return CSR(B.nb * bs, B.mb * bs, np.cumsum(rowptr).astype(np.int32), c.astype(np.int32),
+               np.ascontiguousarray(v, dtype=np.float64))
+
+
+def random_bsr(nb: int, mb: int, bs: int, density: float, *, seed: int, empty_rows: float = 0.0) -> BSR:
+    """Random block pattern (as random_csr) with dense blocks of uniform [-1, 1] values."""
+    pat = random_csr(nb, mb, density, seed=seed, empty_rows=empty_rows)
+    rng = np.random.default_rng(seed + 7919)
+    val = rng.uniform(-1.0, 1.0, size=(pat.nnz, bs, bs))
+    return BSR(nb, mb, bs, pat.rowptr, pat.col, val)
 
 
 # --------------------------------------------------------------------------------------------
