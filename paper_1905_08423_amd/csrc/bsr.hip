@@ -11,6 +11,9 @@
 //   2. every lane fetches row r of its group's U from the lanes holding it (ds_bpermute);
 //   3. for each entry P(J,j) of row J of P the lane adds sum_k U[r][k] P(J,j)[k][c] into block
 //      j of row i of C (LDS FP64 add at the block's position).
+// Blocks are read one entry per lane (the wavefront's load is contiguous); a lane takes the
+// other entries of its column from the lanes holding them (ds_bpermute), which costs the
+// address unit a quarter of loading the column in every lane.
 // The C pattern is the structural block product computed by the scalar symbolic phase on the
 // block patterns.  Summation order varies between runs (LDS and device atomics).
 #include "device.hpp"
@@ -37,6 +40,50 @@ __device__ __forceinline__ int row_find(const int* __restrict__ col, int c0, int
     if (col[c0 + mid] <= j) lo = mid; else hi = mid;
   }
   return lo;
+}
+constexpr int kU = 4;  // products of a step whose loads are issued together
+
+// 4 x 4 blocks: a group of 16 lanes is one DPP row, block row r is quad r.  Rotating the row by
+// 4d lanes brings entry ((r - d) mod 4, c) to lane (r, c), so a column of a block is gathered
+// with three rotations, and row r of a block with four quad broadcasts, all in VALU.
+template <int CTRL>
+__device__ __forceinline__ double dpp_dbl(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kRor4 = 0x124, kRor8 = 0x128, kRor12 = 0x12C;  // row_ror:4, :8, :12
+// sum_k w[k] X[k][c] for lane (r, c), with wr[d] = w[(r - d) mod 4] precomputed
+__device__ __forceinline__ double col_dot4(const double (&wr)[4], double x) {
+  return wr[0] * x + wr[1] * dpp_dbl<kRor4>(x) + wr[2] * dpp_dbl<kRor8>(x) + wr[3] * dpp_dbl<kRor12>(x);
+}
+// w[(r - d) mod 4] for d = 0..3 from the lane's w[0..3]
+__device__ __forceinline__ void rot_coef4(const double (&w)[4], int r, double (&wr)[4]) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const int k = (r - d) & 3;
+    wr[d] = k == 0 ? w[0] : k == 1 ? w[1] : k == 2 ? w[2] : w[3];
+  }
+}
+
+// One step of row I for this lane's group: its entry A(I,J) (this lane's element) and the
+// extent of row J of P.
+struct StepLoad {
+  double own;
+  int ps, pe;
+  bool ok;
+};
+template <int B2, int G>
+__device__ __forceinline__ StepLoad step_load(const BsrArgs& a, int t0, int a1, int g, int ent, bool in_group) {
+  const int t = t0 + g;
+  StepLoad r{0.0, 0, 0, in_group && t < a1};
+  if (r.ok) {
+    const int J = a.A_col[t];
+    r.own = a.A_val[(size_t)t * B2 + ent];
+    r.ps = a.P_rowptr[J];
+    r.pe = a.P_rowptr[J + 1];
+  }
+  return r;
 }
 }  // namespace
 
@@ -92,41 +139,64 @@ __global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_numeric(BsrArgs a, con
     double T[BS];  // lane (r, c): row r of P(I,i)^T, i.e. column r of P(I,i)
 #pragma unroll
     for (int k = 0; k < BS; ++k) T[k] = a.P_val[pIi + k * BS + r];
+    double Tr[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (BS == 4) rot_coef4(T, r, Tr);
     const int a0 = a.A_rowptr[I], a1 = a.A_rowptr[I + 1];
+    // step loads (the entry A(I,J) of this lane's group, the extent of row J of P) are issued
+    // one step ahead; the products of a step issue their loads kU at a time
+    StepLoad nx = step_load<B2, G>(a, a0, a1, g, ent, in_group);
     for (int t0 = a0; t0 < a1; t0 += G) {
-      const int t = t0 + g;
-      const bool ok = in_group && t < a1;
+      const StepLoad cu = nx;
+      if (t0 + G < a1) nx = step_load<B2, G>(a, t0 + G, a1, g, ent, in_group);
       double U = 0.0;
-      int ps = 0, pe = 0;
-      if (ok) {
-        const int J = a.A_col[t];
-        const double* __restrict__ Ab = a.A_val + (size_t)t * B2;
-#pragma unroll
-        for (int k = 0; k < BS; ++k) U += T[k] * Ab[k * BS + c];
-        ps = a.P_rowptr[J];
-        pe = a.P_rowptr[J + 1];
-      }
       double Ur[BS];  // row r of this group's U
+      double Urr[4] = {0.0, 0.0, 0.0, 0.0};
+      if constexpr (BS == 4) {
+        U = col_dot4(Tr, cu.own);
+        Ur[0] = dpp_dbl<0x00>(U);
+        Ur[1] = dpp_dbl<0x55>(U);
+        Ur[2] = dpp_dbl<0xAA>(U);
+        Ur[3] = dpp_dbl<0xFF>(U);
+        rot_coef4(Ur, r, Urr);
+      } else {
 #pragma unroll
-      for (int k = 0; k < BS; ++k) Ur[k] = lane_dbl(U, in_group ? g * B2 + r * BS + k : ln);
-      const int len = pe - ps;
+        for (int k = 0; k < BS; ++k) U += T[k] * lane_dbl(cu.own, in_group ? g * B2 + k * BS + c : ln);
+#pragma unroll
+        for (int k = 0; k < BS; ++k) Ur[k] = lane_dbl(U, in_group ? g * B2 + r * BS + k : ln);
+      }
+      const int len = cu.pe - cu.ps;
       const int lmax = wave_max(len);
-      for (int u = 0; u < lmax; ++u) {
-        if (ok && u < len) {
-          const int e2 = ps + u;
-          const int j = a.P_col[e2];
-          const double* __restrict__ Pb = a.P_val + (size_t)e2 * B2;
-          double V = 0.0;
+      for (int u0 = 0; u0 < lmax; u0 += kU) {
+        double pown[kU];
+        int jj[kU];
 #pragma unroll
-          for (int k = 0; k < BS; ++k) V += Ur[k] * Pb[k * BS + c];
-          if (LDS_ACC) {
-            // j is a column of row i by construction of the pattern; the probe is bounded anyway
-            unsigned s = hslot(j, (int)shift);
-            for (int it = 1; keys[s] != j && it < cap; ++it) s = (s + 1) & (unsigned)(cap - 1);
-            if (keys[s] == j) atomicAdd(acc + (size_t)pos[s] * B2 + ent, V);
+        for (int v = 0; v < kU; ++v) {
+          const bool live = cu.ok && u0 + v < len;
+          const int e2 = cu.ps + u0 + v;
+          pown[v] = live ? a.P_val[(size_t)e2 * B2 + ent] : 0.0;
+          jj[v] = live ? a.P_col[e2] : -1;
+        }
+#pragma unroll
+        for (int v = 0; v < kU; ++v) {
+          if (u0 + v >= lmax) break;
+          double V = 0.0;
+          if constexpr (BS == 4) {
+            V = col_dot4(Urr, pown[v]);
           } else {
-            const int p = row_find(a.C_col, c0, nc, j);
-            atomicAdd(a.C_val + ((size_t)c0 + p) * B2 + ent, V);
+#pragma unroll
+            for (int k = 0; k < BS; ++k) V += Ur[k] * lane_dbl(pown[v], in_group ? g * B2 + k * BS + c : ln);
+          }
+          const int j = jj[v];
+          if (j >= 0) {
+            if (LDS_ACC) {
+              // j is a column of row i by construction of the pattern; the probe is bounded anyway
+              unsigned s = hslot(j, (int)shift);
+              for (int it = 1; keys[s] != j && it < cap; ++it) s = (s + 1) & (unsigned)(cap - 1);
+              if (keys[s] == j) atomicAdd(acc + (size_t)pos[s] * B2 + ent, V);
+            } else {
+              const int p = row_find(a.C_col, c0, nc, j);
+              atomicAdd(a.C_val + ((size_t)c0 + p) * B2 + ent, V);
+            }
           }
         }
       }
