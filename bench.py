@@ -215,6 +215,7 @@ def main():
             out["peak_extra_mb"]["twostep"] / max(out["peak_extra_mb"]["merged_owner"], 1e-9), 2)
         out["fwd_bwd_ms"] = fwd_bwd(lib, gen, torch, dev)
         out["batched"] = batched(lib, gen, torch, dev)
+        out["block_4x4"] = block_workload(lib, gen, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, P, B)
@@ -280,6 +281,58 @@ def _time_events(fn, reps, torch):
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def block_workload(lib, gen, torch, dev):
+    """The 4x4-block system (96^3 nodes, anisotropic 27-point couplings, block smoothed
+    aggregation): the block-sparse plan against the scalar plan on the expanded matrices."""
+    A, P, _ = gen.galerkin_workload("c3c")
+    Ab, Pb = gen.csr_to_bsr(A, 4), gen.csr_to_bsr(P, 4)
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    res = {"workload": "96^3_nodes_4x4_blocks_27pt_aniso_lognormal_seed2_block_SA_3x3x3",
+           "n_scalar": A.n_rows, "nnz_A_scalar": A.nnz, "nnz_A_blocks": Ab.nnzb, "nnz_P_blocks": Pb.nnzb}
+
+    def run(plan, Av, Pv, reps):
+        C = plan.numeric(Av, Pv)
+        plan.numeric(Av, Pv, C)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.numeric(Av, Pv, C)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, plan.stats()
+
+    for name, mk, vals, reps in (
+            ("bsr", lambda: lib.Plan(Ab.nb, Pb.mb, d(Ab.rowptr, torch.int32), d(Ab.col, torch.int32),
+                                     d(Pb.rowptr, torch.int32), d(Pb.col, torch.int32), block_size=4),
+             (Ab.val.reshape(-1), Pb.val.reshape(-1)), 10),
+            ("scalar", lambda: lib.Plan(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
+                                        d(P.rowptr, torch.int32), d(P.col, torch.int32)),
+             (A.val, P.val), 3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = mk()
+        torch.cuda.synchronize()
+        sym = (time.perf_counter() - t0) * 1e3
+        Av, Pv = d(vals[0], torch.float64), d(vals[1], torch.float64)
+        ms, st = run(plan, Av, Pv, reps)
+        res[name + "_numeric_ms"] = round(ms, 3)
+        res[name + "_symbolic_ms"] = round(sym, 1)
+        res[name + "_plan_peak_mb"] = round(st["peak_bytes"] / 2**20, 1)
+        if name == "bsr":
+            b2 = 16
+            Bb = ((4 + 8 * b2) * Ab.nnzb + 4 * (Ab.nb + 1) + (4 + 8 * b2) * Pb.nnzb + 4 * (Pb.nb + 1)
+                  + 8 * b2 * st["nnz_C"])
+            res["bsr_algorithmic_bytes"] = Bb
+            res["bsr_GBps"] = round(Bb / ms / 1e6, 1)
+        print(f"# block 4x4 {name}: numeric {ms:.2f} ms, symbolic {sym:.0f} ms", file=sys.stderr, flush=True)
+        plan.close()
+        del Av, Pv
+        torch.cuda.empty_cache()
+    res["speedup_bsr_over_scalar"] = round(res["scalar_numeric_ms"] / res["bsr_numeric_ms"], 2)
+    return res
 
 
 def batched(lib, gen, torch, dev):
