@@ -216,6 +216,7 @@ def main():
         out["fwd_bwd_ms"] = fwd_bwd(lib, gen, torch, dev)
         out["batched"] = batched(lib, gen, torch, dev)
         out["block_4x4"] = block_workload(lib, gen, torch, dev)
+        out["smoothed_aggregation_96cubed"] = sa_workloads(lib, gen, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, P, B)
@@ -281,6 +282,50 @@ def _time_events(fn, reps, torch):
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def sa_workloads(lib, gen, torch, dev):
+    """96^3 anisotropic 27-point operator (eps 0.01 in z, lognormal seed 2) with smoothed
+    aggregation (3x3x3 aggregates; one and two damped-Jacobi steps): merged all-at-once against
+    two-step, numeric time, GB/s over the algorithmic bytes and peak extra memory."""
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    res = {}
+    for name, label in (("c3a", "one_jacobi_step"), ("c3b", "two_jacobi_steps")):
+        A, P, _ = gen.galerkin_workload(name)
+        r = {"n": A.n_rows, "m": P.n_cols, "nnz_A": A.nnz, "nnz_P": P.nnz}
+        Av, Pv = d(A.val, torch.float64), d(P.val, torch.float64)
+        pats = [d(A.rowptr, torch.int32), d(A.col, torch.int32), d(P.rowptr, torch.int32), d(P.col, torch.int32)]
+        for algo in ("merged", "twostep"):
+            torch.cuda.synchronize()
+            base = torch.cuda.memory_allocated()
+            torch.cuda.reset_peak_memory_stats()
+            plan = lib.Plan(A.n_rows, P.n_cols, *pats, algo=algo)
+            C = plan.numeric(Av, Pv)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            extra = torch.cuda.max_memory_allocated() - base - 8 * st["nnz_C"] - st["pattern_bytes"]
+            for _ in range(2):
+                plan.numeric(Av, Pv, C)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                plan.numeric(Av, Pv, C)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            B = algorithmic_bytes(A.n_rows, A.nnz, P.nnz, st["nnz_C"])
+            r["nnz_C"] = st["nnz_C"]
+            r[algo + "_numeric_ms"] = round(ms, 3)
+            r[algo + "_GBps"] = round(B / ms / 1e6, 1)
+            r[algo + "_peak_extra_mb"] = round(extra / 2**20, 1)
+            print(f"# SA {label} {algo}: numeric {ms:.3f} ms, peak extra {extra / 2**20:.1f} MB",
+                  file=sys.stderr, flush=True)
+            plan.close()
+            del C
+            torch.cuda.empty_cache()
+        res[label] = r
+    return res
 
 
 def block_workload(lib, gen, torch, dev):
@@ -378,15 +423,25 @@ def batched(lib, gen, torch, dev):
         p.close()
     del C, Cp, A_vals, A_plain, keep, Pv
     torch.cuda.empty_cache()
-    # (ii) independent problems
+    # (ii) independent problems; plan options tuned by measurement on the largest of them
     sides3 = gen.batch_problem_sides(64, seed=3, lo=12, hi=64)
-    plans, Av, Pv, keep = [], [], [], []
+    probs = []
     for k, (nx, ny, nz) in enumerate(sides3):
         A = gen.stencil27(int(nx), int(ny), int(nz), seed=1000 + k)
         P = gen.trilinear(int(nx), int(ny), int(nz))
+        probs.append((A, P))
+    big = max(range(len(probs)), key=lambda k: probs[k][0].nnz)
+    A, P = probs[big]
+    tp, report = lib.tune(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
+                          d(P.rowptr, torch.int32), d(P.col, torch.int32), d(A.val, torch.float64),
+                          d(P.val, torch.float64), candidates=lib.TUNE_CANDIDATES[:4], base={"algo": "merged"})
+    tuned = tp.tuned_options
+    tp.close()
+    plans, Av, Pv, keep = [], [], [], []
+    for A, P in probs:
         t = (d(A.rowptr, torch.int32), d(A.col, torch.int32), d(P.rowptr, torch.int32), d(P.col, torch.int32))
         keep.append(t)
-        plans.append(lib.Plan(A.n_rows, P.n_cols, *t, algo="merged"))
+        plans.append(lib.Plan(A.n_rows, P.n_cols, *t, **tuned))
         Av.append(d(A.val, torch.float64))
         Pv.append(d(P.val, torch.float64))
     C = [torch.empty(p.nnz_C, dtype=torch.float64, device=dev) for p in plans]
@@ -402,7 +457,8 @@ def batched(lib, gen, torch, dev):
     diff = max(float(((c - cp).abs().max() / cp.abs().max().clamp_min(1e-300)).item()) for c, cp in zip(C, Cp))
     res["independent_64_sides_12_64"] = {"products": len(plans), "fine_rows": int(sum(p.n for p in plans)),
                                          "plain_ms": round(t_plain, 4), "batched_graph_ms": round(t_batch, 4),
-                                         "max_rel_diff_vs_plain": diff}
+                                         "max_rel_diff_vs_plain": diff, "tuned_options": tuned,
+                                         "tuning": report}
     batch.close()
     for p in plans:
         p.close()

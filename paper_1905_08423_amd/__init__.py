@@ -420,6 +420,52 @@ class Batch:
             pass
 
 
+# Option sets tried by tune(): workgroup size and tile budget of the owner fold (the LDS "bins"
+# the tiles are sized for), the atomic fold, and the numeric cache.
+TUNE_CANDIDATES = (
+    {},
+    {"owner_waves": 8},
+    {"tile_lds": 98304},
+    {"tile_lds": 65536},
+    {"cache": True},
+    {"fold": "atomic"},
+)
+
+
+def tune(n, m, A_rowptr, A_col, P_rowptr, P_col, A_val, P_val, *, candidates=TUNE_CANDIDATES,
+         reps=3, base=None, stream=None):
+    """Choose plan options by measurement: build a plan per candidate option set (merged with
+    the given base options), time `reps` numeric products of each on the given values with HIP
+    events, and return (best plan, report).  The other plans are destroyed.  The results of all
+    candidates are the same product (the options change only how it is computed)."""
+    base = dict(base or {})
+    report = []
+    best = None
+    strm = stream if stream is not None else torch.cuda.current_stream()
+    for cand in candidates:
+        opts = {**base, **cand}
+        plan = Plan(n, m, A_rowptr, A_col, P_rowptr, P_col, stream=stream, **opts)
+        C = plan.numeric(A_val, P_val, stream=stream)
+        plan.numeric(A_val, P_val, C, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(strm)
+        for _ in range(reps):
+            plan.numeric(A_val, P_val, C, stream=stream)
+        e1.record(strm)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        report.append({"options": opts, "numeric_ms": round(ms, 4)})
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[1].close()
+            best = (ms, plan, opts)
+        else:
+            plan.close()
+        del C
+    best[1].tuned_options = best[2]
+    return best[1], report
+
+
 class PtAPFunction(torch.autograd.Function):
     """C_val = PtAP(A_val, P_val) on a plan's fixed patterns; backward through ptap_backward
     (dA = P dC P^T on A's pattern, dP = A P dC^T + A^T P dC on P's pattern)."""

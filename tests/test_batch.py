@@ -150,3 +150,22 @@ def test_batch_rejects_changed_pointers_and_bad_plans():
     two.close()
     for p in plans:
         p.close()
+
+
+def test_tune_picks_a_measured_plan_with_the_same_product():
+    """tune(): every candidate plan computes the same product; the returned plan is the fastest
+    candidate of the report and its result matches the oracle."""
+    import oracle
+    from helpers import assert_close
+    A, P = gen.stencil27(20, seed=3), gen.trilinear(20)
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).cuda()  # noqa: E731
+    Av, Pv = d(A.val, torch.float64), d(P.val, torch.float64)
+    plan, report = lib.tune(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
+                            d(P.rowptr, torch.int32), d(P.col, torch.int32), Av, Pv, reps=2)
+    assert len(report) == len(lib.TUNE_CANDIDATES)
+    best = min(report, key=lambda r: r["numeric_ms"])
+    assert plan.tuned_options == best["options"]
+    C = plan.numeric(Av, Pv).cpu().numpy()
+    ref = oracle.ptap(A, P)
+    assert_close(C, ref.val, ref.abs)
+    plan.close()
