@@ -198,6 +198,7 @@ struct ptap_plan {
   bool sym_done = false;
   int lds_budget = 65536;
   int lds_device = 65536;  // LDS bytes one workgroup may use on this device
+  int n_cu = 256;          // compute units of this device
   int owner_waves = kFastWaves;
   int lds_hash_max = kLdsHashMax;
   int lds_keys_max = kLdsKeysMax;
@@ -341,6 +342,9 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
     hipck(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     p->lds_budget = std::min(lds, 65536);
     p->lds_device = lds;
+    int cus = 0;
+    hipck(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    p->n_cu = std::max(1, cus);
     if (o.hash_slots) {
       p->lds_hash_max = std::min(p->lds_hash_max, (int)o.hash_slots);
       p->lds_keys_max = std::min(p->lds_keys_max, (int)o.hash_slots);
@@ -637,7 +641,18 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         room = ((long long)lds_tile - (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) + (long long)cap_all * 12) -
                 (TR + 1) * 4LL - 16) / 12;
       int TE = (int)std::max<long long>(16, room);
-      if (P->opt.tile_entries) TE = std::min(TE, (int)P->opt.tile_entries);
+      if (P->opt.tile_entries) {
+        TE = std::min(TE, (int)P->opt.tile_entries);
+      } else if (!P->opt.tile_lds) {
+        // Fewer tiles than resident workgroups (two per CU) leave CUs idle: shrink the tiles until
+        // they fill about 95% of one round of workgroups (not more, or a few tiles run alone in
+        // a second round), accepting the extra rows of AP that smaller tiles form twice.
+        const long long slots = 2LL * P->n_cu;
+        if (P->nnzC / TE < slots) {
+          const long long te_par = (P->nnzC * 100) / (95 * slots);
+          TE = (int)std::min<long long>(TE, std::max<long long>(te_par, 256));
+        }
+      }
       P->TE = TE;
       std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
       std::vector<int> tptr, trows;
@@ -771,6 +786,7 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
     fresh.nnzP = plan->nnzP;
     fresh.lds_budget = plan->lds_budget;
     fresh.lds_device = plan->lds_device;
+    fresh.n_cu = plan->n_cu;
     fresh.owner_waves = plan->owner_waves;
     fresh.lds_hash_max = plan->lds_hash_max;
     fresh.lds_keys_max = plan->lds_keys_max;
