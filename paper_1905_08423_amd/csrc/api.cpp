@@ -737,25 +737,47 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     }
   }
 
-  // --- Adjoint row classes: U_I has at most sum_{i in P(I,:)} |C(i,:)| keys.
+  // --- Adjoint row classes.  U_I has the distinct columns of the rows of C under P(I,:) as keys
+  // (R_I's columns are among them); they are counted exactly on the host.  Rows whose rows of C
+  // under P(I,:) hold at most kAdjMaxWalk entries in total go to the short-row kernel.
   if (P->opt.backward) {
-    std::vector<int> rows(n);
-    std::vector<long long> need(n);
-    // |U_I| <= min(m, sum over P(I,:) of row lengths of C): computed from P's columns on host.
     std::vector<int> hPcol = to_host(pat.P_col, (size_t)P->nnzP, s);
+    std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
+    const int lds_max = lmax / 2 >= 64 ? lmax / 2 : 64;
+    std::vector<int> mark(m, -1), frows, grows;
+    std::vector<long long> fneed, gneed;
     for (int I = 0; I < n; ++I) {
-      rows[I] = I;
-      long long u = 0;
-      for (int e = hP_rowptr[I]; e < hP_rowptr[I + 1]; ++e)
-        u += h_c_ptr[hPcol[e] + 1] - h_c_ptr[hPcol[e]];
-      u = std::min<long long>(u, m);
-      // rows with an empty A row still need their (empty) dA written: nothing to do for them.
-      need[I] = std::max<long long>(std::max<long long>(u, hr[I]), 1);
+      long long walk = 0, distinct = 0;
+      for (int e = hP_rowptr[I]; e < hP_rowptr[I + 1]; ++e) {
+        const int i = hPcol[e];
+        walk += h_c_ptr[i + 1] - h_c_ptr[i];
+        for (int c = h_c_ptr[i]; c < h_c_ptr[i + 1]; ++c)
+          if (mark[h_c_col[c]] != I) {
+            mark[h_c_col[c]] = I;
+            ++distinct;
+          }
+      }
+      const int np = hP_rowptr[I + 1] - hP_rowptr[I];
+      const long long need = std::max<long long>(std::max<long long>(distinct, hr[I]), 1);
+      // a row with an empty row of P contributes nothing (dA is zeroed before the launch)
+      if (np == 0) continue;
+      const int cap = cap_for(need);
+      if (np <= kAdjMaxSegs && walk <= kAdjMaxWalk && cap <= std::min(kAdjMaxCap, lds_max)) {
+        frows.push_back(I);
+        fneed.push_back(need);
+      } else {
+        grows.push_back(I);
+        gneed.push_back(need);
+      }
     }
-    // the adjoint kernel holds two tables of this capacity per wavefront
-    P->bwd_rows = make_classes(t, rows, need, lmax / 2 >= 64 ? lmax / 2 : 64, s);
+    // the general kernel holds two tables of this capacity per wavefront
+    P->bwd_rows = make_classes(t, grows, gneed, lds_max, s);
     spill_need_ints = std::max(spill_need_ints, spill_ints(P->bwd_rows, 2));
     spill_need_vals = std::max(spill_need_vals, spill_ints(P->bwd_rows, 2));
+    for (RowClass& c : make_classes(t, frows, fneed, lds_max, s)) {
+      c.fast = true;
+      P->bwd_rows.push_back(c);
+    }
   }
 
   t.put(r);
@@ -889,7 +911,9 @@ ptap_status ptap_backward(ptap_plan* P, const double* A_val, const double* P_val
     if (dP_val) hipck(launch_fill_f64(dP_val, 0.0, P->nnzP, s));
     if (!dA_val && !dP_val) return PTAP_OK;
     NumericArgs a = numeric_args(P, A_val, P_val, nullptr, PART_ALL);
-    for (auto& c : P->bwd_rows) hipck(launch_backward(a, dC_val, dA_val, dP_val, c, P->gtab, P->gval, s));
+    for (auto& c : P->bwd_rows)
+      hipck(c.fast ? launch_backward_short(a, dC_val, dA_val, dP_val, c, s)
+                   : launch_backward(a, dC_val, dA_val, dP_val, c, P->gtab, P->gval, s));
   } catch (const Failure& f) {
     return f.status;
   }

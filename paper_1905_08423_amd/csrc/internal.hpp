@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/ptap.h"
@@ -16,6 +17,7 @@ namespace ptapk {
 struct RowClass {
   int cap = 0;
   bool global = false;
+  bool fast = false;  // adjoint: short-row kernel (adjoint.hip)
   int count = 0;
   int* rows = nullptr;  // device, `count` row indices in ascending order
 };
@@ -147,5 +149,14 @@ hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double
 // Adjoint.
 hipError_t launch_backward(const NumericArgs& a, const double* dC, double* dA, double* dP,
                            const RowClass& rc, int* gtab, double* gval, hipStream_t s);
+// Short-row adjoint (adjoint.hip): rows with 1..kAdjMaxSegs entries in P(I,:), at most
+// kAdjMaxWalk entries in the rows of dC under them, and a table of at most kAdjMaxCap slots.
+constexpr int kAdjPasses = 4;
+constexpr int kAdjMaxWalk = kAdjPasses * WAVE;
+constexpr int kAdjMaxSegs = WAVE;
+constexpr int kAdjMaxCap = 512;
+size_t backward_short_lds_bytes(int cap);
+hipError_t launch_backward_short(const NumericArgs& a, const double* dC, double* dA, double* dP,
+                                 const RowClass& rc, hipStream_t s);
 
 }  // namespace ptapk

@@ -40,8 +40,11 @@ def _gpu_backward(g, plan, W):
     return dA.cpu().numpy(), dP.cpu().numpy()
 
 
-@pytest.mark.parametrize("case", ["random", "c5_8", "c5_12", "sa2_9", "toy"])
+@pytest.mark.parametrize("case", ["random", "c5_8", "c5_12", "c5_12_spill", "sa2_9", "toy", "wide"])
 def test_backward_against_oracle(case):
+    """Rows with short walks over dC take the short-row kernel, the others the general one;
+    c5_12_spill caps on-chip tables at 64 slots, so most rows use device-memory tables."""
+    kw = {}
     if case == "random":
         A = gen.random_csr(200, 200, 0.03, seed=3, empty_rows=0.1, explicit_zeros=0.05)
         P = gen.random_csr(200, 40, 0.08, seed=4, empty_rows=0.1, zero_cols=2)
@@ -51,11 +54,18 @@ def test_backward_against_oracle(case):
         s = int(case.split("_")[1])
         A = gen.stencil27(s, seed=2, eps_z=0.01)
         P = gen.smoothed_aggregation(A, s, s, s, steps=2)
+    elif case == "wide":
+        # a small coarse space with long rows of C: a quarter of the rows walk 65..256 entries
+        # of dC (two to four passes), the rest walk more and take the general kernel
+        A = gen.random_csr(300, 300, 0.01, seed=11, empty_rows=0.05)
+        P = gen.random_csr(300, 60, 0.1, seed=12, empty_rows=0.05)
     else:
         s = int(case.split("_")[1])
         A, P = gen.stencil27(s, seed=4), gen.trilinear(s)
+        if case.endswith("spill"):
+            kw["hash_slots"] = 64
     g = GpuProblem(A, P)
-    plan = g.plan(algo="merged", backward=True)
+    plan = g.plan(algo="merged", backward=True, **kw)
     rp, col = (t.cpu().numpy() for t in plan.pattern())
     W = gen.loss_weights(plan.nnz_C, seed=5)
     dA, dP = _gpu_backward(g, plan, W)
