@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline numeric (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="time only the differentiable form (forward + adjoint, for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of known size (counter calibration) and exit")
     return ap.parse_args()
@@ -98,6 +100,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+        return
+
+    if args.fwd_bwd_only:
+        print(json.dumps(fwd_bwd(lib, gen, torch, dev)))
         return
 
     t0 = time.time()
