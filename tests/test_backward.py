@@ -40,7 +40,46 @@ def _gpu_backward(g, plan, W):
     return dA.cpu().numpy(), dP.cpu().numpy()
 
 
-@pytest.mark.parametrize("case", ["random", "c5_8", "c5_12", "c5_12_spill", "sa2_9", "toy", "wide"])
+def _grouped(seed=3):
+    """Coarse columns in groups of g; every row of C is its whole group (a fine row per group
+    holds all g entries, A couples fine rows of one group only).  A fine row with np entries in
+    a group of g walks np*g entries of dC, so g = 16 gives walks 16, 64, 128, 192, 256 whose
+    segments end exactly on 64-lane pass boundaries, g = 64 one segment per pass, and g = 17,
+    65 rows just past 256 (general kernel) beside rows at 255.  Also rows with an empty row of P
+    and a row with an empty row of A."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    groups = [(16, [1, 4, 8, 12, 16, 0]), (17, [15, 16, 17]), (64, [1, 2, 4]), (65, [4, 1]),
+              (16, [16, 8, 4])]
+    prow, pcol, members = [], [], []
+    c0 = I = 0
+    for g, nps in groups:
+        rows = []
+        for npi in [g] + nps:
+            cols = np.sort(rng.choice(g, size=npi, replace=False)) + c0
+            prow += [I] * npi
+            pcol += list(cols)
+            rows.append(I)
+            I += 1
+        members.append(rows)
+        c0 += g
+    n, m = I + 1, c0  # the last fine row has a row of P but none of A
+    prow += [I, I]
+    pcol += [0, 1]
+    P = sp.csr_matrix((rng.uniform(-1, 1, len(prow)), (prow, pcol)), shape=(n, m))
+    arow, acol = [], []
+    for rows in members:
+        for a in rows:
+            for b in rows:
+                if a == b or rng.random() < 0.5:
+                    arow.append(a)
+                    acol.append(b)
+    A = sp.csr_matrix((rng.uniform(-1, 1, len(arow)), (arow, acol)), shape=(n, n))
+    return gen.from_scipy(A), gen.from_scipy(P)
+
+
+@pytest.mark.parametrize("case", ["random", "c5_8", "c5_12", "c5_12_spill", "sa2_9", "toy", "wide",
+                                  "grouped"])
 def test_backward_against_oracle(case):
     """Rows with short walks over dC take the short-row kernel, the others the general one;
     c5_12_spill caps on-chip tables at 64 slots, so most rows use device-memory tables."""
@@ -54,6 +93,8 @@ def test_backward_against_oracle(case):
         s = int(case.split("_")[1])
         A = gen.stencil27(s, seed=2, eps_z=0.01)
         P = gen.smoothed_aggregation(A, s, s, s, steps=2)
+    elif case == "grouped":
+        A, P = _grouped()
     elif case == "wide":
         # a small coarse space with long rows of C: a quarter of the rows walk 65..256 entries
         # of dC (two to four passes), the rest walk more and take the general kernel
