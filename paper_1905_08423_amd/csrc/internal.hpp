@@ -142,6 +142,25 @@ hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int
                              hipStream_t s);
 hipError_t launch_gather(const double* src, const int* idx, double* dst, long long count,
                          hipStream_t s);
+// Short-row form of both two-step products (rowmul.hip): O(r,:) = sum_k X(r,k) Y(k,:) into O's
+// stored pattern, for rows with at most 32 entries in X(r,:) and in O(r,:).  O has nX rows.
+struct RowMulArgs {
+  const int* X_rowptr;
+  const int* X_col;
+  const double* X_val;
+  const int* Y_rowptr;
+  const int* Y_col;
+  const double* Y_val;
+  const int* O_rowptr;
+  const int* O_col;
+  double* O_val;
+  int nX, nY;
+  long long nnzX, nnzY, nnzO;
+};
+constexpr int kRowMulMaxLen = 32;
+bool rowmul_short_fits(const RowMulArgs& g);  // byte extents within the 32-bit buffer range
+hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, int n_cu,
+                               hipStream_t s);
 hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double* PT_val,
                               const int* AP_rowptr, const int* AP_col, const double* AP_val,
                               const int* C_rowptr, const int* C_col, double* C_val,

@@ -16,70 +16,15 @@
 // row pairs of a wavefront are software-pipelined (see the loop).
 #include "device.hpp"
 #include "internal.hpp"
+#include "short_rows.hpp"
 
 namespace ptapk {
 
 namespace {
-constexpr int kHalf = 32;
-constexpr int kCap = 64;  // slots of one R_I table (|R_I| <= 32, load <= 1/2)
-constexpr int kCapShift = 32 - 6;
 constexpr int kPrefetch = 4;  // product-walk steps whose loads are issued together
-
-// Record of one nonempty segment of the product walk (one A entry of the row): its weight
-// A(I,J) and the offset that turns a product number k of the row into the index k + base of
-// P's entry.  The fold reuses the records for the owned entries: weight P(I,i), and the start
-// (base) and end (pad) of row i of the tile.
-struct SegRec {
-  double w;
-  int base;
-  int pad;
-};
-
-struct HalfScratch {
-  int keys[2][kCap];
-  double vals[2][kCap];
-  SegRec rec[2][kHalf];
-};
 }  // namespace
 
 size_t owner_fast_wave_bytes() { return sizeof(HalfScratch); }
-
-// Raw buffer resources: 32-bit byte offsets instead of 64-bit addresses, one 8-byte load for a
-// pair of row pointers, and reads past the end of an array return 0 instead of faulting.  The
-// texture address unit handles a 4-byte load at 16 lanes per cycle but an 8-byte one at 4 lanes
-// per cycle even when the lanes share an address, so values needed by a whole half-wavefront
-// (a row's index and extents) are loaded by one lane and broadcast with readlane.
-typedef unsigned v2u __attribute__((ext_vector_type(2)));
-constexpr int kRawBufferFlags = 0x00020000;  // 32-bit data format, no swizzle
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
-                                           kRawBufferFlags);
-}
-__device__ __forceinline__ v2u ld_pair(__amdgpu_buffer_rsrc_t r, int idx) {
-  return __builtin_amdgcn_raw_buffer_load_b64(r, idx * 4, 0, 0);
-}
-
-// Inclusive prefix sum (or prefix OR) over each 32-lane half of the wavefront, in VALU only:
-// DPP row shifts by 1, 2, 4, 8 scan each 16-lane row, then lane 15 of rows 0 and 2 is broadcast
-// into rows 1 and 3.  Lanes whose source lies outside the row keep the identity (old = 0).
-// Every lane of the wavefront must be active.
-__device__ __forceinline__ int half_incl_scan(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
-  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-  return v;
-}
-__device__ __forceinline__ int half_or_scan(int v) {
-  v |= __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);
-  v |= __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);
-  v |= __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);
-  v |= __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);
-  v |= __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
-  return v;
-}
 
 // Per-lane state of one fine row at the successive stages of the pipelined loop (one row per
 // 32-lane half; lane `sub` follows the row's A entry a0+sub and P entry p0+sub).
@@ -126,13 +71,6 @@ __device__ __forceinline__ Stage2 hdr_get(const Stage2& b, int k, int half) {
   r.p1 = __builtin_amdgcn_ds_bpermute(src, b.p1);
   return r;
 }
-__device__ __forceinline__ int ld_col(__amdgpu_buffer_rsrc_t r, int idx) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
-}
-__device__ __forceinline__ double ld_dbl(__amdgpu_buffer_rsrc_t r, int idx) {
-  const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
-  return __hiloint2double((int)v[1], (int)v[0]);
-}
 
 // Buffer resources of the arrays the kernel gathers from.  Every gather below is issued
 // unconditionally: an invalid entry passes index -1, whose byte offset lies past the end of the
@@ -142,9 +80,6 @@ __device__ __forceinline__ double ld_dbl(__amdgpu_buffer_rsrc_t r, int idx) {
 struct Gather {
   __amdgpu_buffer_rsrc_t A_rowptr, P_rowptr, A_col, P_col, P_val, A_val, slot, pext;
 };
-__device__ __forceinline__ int ld_i32(__amdgpu_buffer_rsrc_t r, int idx) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0);
-}
 
 template <bool PEXT>
 __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Gather& g, int sub) {
@@ -171,56 +106,6 @@ __device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Gather& g) {
   r.sl = q.e >= 0 ? sl : -1;
   r.pw = ld_dbl(g.P_val, q.e);
   return r;
-}
-
-// The value of lane 31 (half 0) or lane 63 (half 1): the half's total after a scan.
-__device__ __forceinline__ int half_total(int v, int half) {
-  const int t0 = __builtin_amdgcn_readlane(v, 31), t1 = __builtin_amdgcn_readlane(v, 63);
-  return half ? t1 : t0;
-}
-
-// One step of the flattened product walk of a half: product k = 32 st + sub of the row (if it
-// exists) is entry k + base of P, weighted by A(I,J) of its segment.  `before` counts the
-// nonempty segments ending at or before the step's window and is advanced past it.
-struct ProdLoad {
-  int j;     // column of P's entry (0 where there is no product)
-  double v;  // value of P's entry
-  double w;  // A(I,J)
-  bool ok;   // the product exists (tested only where it is inserted, so that the loads of
-             // several steps stay in flight together)
-};
-__device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th, int sub, int half,
-                                              int& before, const SegRec* rec,
-                                              __amdgpu_buffer_rsrc_t rPc, __amdgpu_buffer_rsrc_t rPv) {
-  const int k0 = st * kHalf;
-  const int d = incl - k0 - 1;
-  const int bit = (len > 0 && (unsigned)d < (unsigned)kHalf) ? (int)(1u << d) : 0;
-  const unsigned ends = (unsigned)half_total(half_or_scan(bit), half);
-  const int k = k0 + sub;
-  const int rk = (before + __popc(ends & ((1u << sub) - 1u))) & (kHalf - 1);
-  const SegRec rc = rec[rk];
-  const int e = k < Th ? k + rc.base : -1;
-  ProdLoad r{ld_col(rPc, e), ld_dbl(rPv, e), rc.w, k < Th};
-  before += __popc(ends);
-  return r;
-}
-
-// R_I(key) += v in a 64-slot LDS table.  A plain read finds keys already present (most of a
-// row's products hit a key inserted before), so only first insertions use compare-and-swap.
-// The probe is bounded by the table size (a half never holds more than 32 keys, so the bound is
-// never reached).
-__device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
-  unsigned s = hslot(key, kCapShift);
-#pragma unroll 1  // rarely more than one probe: unrolling only adds exec-mask bookkeeping
-  for (int it = 0; it < kCap; ++it) {
-    int seen = keys[s];
-    if (seen == EMPTY) seen = atomicCAS(keys + s, EMPTY, key);
-    if (seen == EMPTY || seen == key) {
-      atomicAdd(vals + s, v);
-      return;
-    }
-    s = (s + 1) & (kCap - 1);
-  }
 }
 
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the

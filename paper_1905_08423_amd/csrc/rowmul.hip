@@ -1,0 +1,168 @@
+// Row-times-matrix products into a known output pattern, short-row form: the two numeric
+// products of the two-step method (Alg. 6),
+//   AP = A P          X = A,    Y = P,   O = AP   (the stored auxiliary matrix, Alg. 4 rows)
+//   C  = P^T (AP)     X = P^T,  Y = AP,  O = C    (rows of P^T: the column lists of P with the
+//                                                  gathered values of its entries)
+// each row O(r,:) = sum_k X(r,k) Y(k,:) written into O's stored, sorted pattern.
+//
+// Two rows per wavefront, one per 32-lane half, in the manner of the owner fold's short-row
+// kernel: lane `sub` holds X(r, x0+sub) and the extent of row k of Y; the products X(r,k) Y(k,j)
+// are dealt out 32 per step over the half (a prefix sum of the lengths of the rows of Y gives each
+// lane its product and its segment), the gathers of four steps are issued together, and the
+// products are added into the half's 64-slot LDS table.  Then the half reads O's row pattern and
+// writes each value it finds.  Rows with at most 32 entries in X(r,:) and in O(r,:); longer rows
+// take the general kernels.  A wavefront works through a contiguous run of row pairs, whose row
+// headers (row, extents in X and in O) lane h*32+k loads for iteration it0+k once per 32
+// iterations.
+#include "internal.hpp"
+#include "short_rows.hpp"
+
+namespace ptapk {
+namespace {
+
+constexpr int kRmWaves = 8;
+constexpr int kRmPrefetch = 4;  // product-walk steps whose loads are issued together
+
+struct RmHeader {
+  int r, x0, x1, o0, o1;  // row of O (or -1), its extents in X and in O
+};
+
+__device__ __forceinline__ RmHeader rm_hdr_get(const RmHeader& b, int k, int half) {
+  const int src = (half * kHalf + k) * 4;
+  RmHeader h;
+  h.r = __builtin_amdgcn_ds_bpermute(src, b.r);
+  h.x0 = __builtin_amdgcn_ds_bpermute(src, b.x0);
+  h.x1 = __builtin_amdgcn_ds_bpermute(src, b.x1);
+  h.o0 = __builtin_amdgcn_ds_bpermute(src, b.o0);
+  h.o1 = __builtin_amdgcn_ds_bpermute(src, b.o1);
+  return h;
+}
+
+__global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
+                                                                  const int* __restrict__ rows,
+                                                                  int count, int pairs_per_wave) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int half = ln / kHalf, sub = ln % kHalf;
+  HalfScratch* hs = reinterpret_cast<HalfScratch*>(smem) + wid;
+  int* keys = hs->keys[half];
+  double* vals = hs->vals[half];
+  keys[sub] = EMPTY;
+  keys[sub + kHalf] = EMPTY;
+  vals[sub] = 0.0;
+  vals[sub + kHalf] = 0.0;
+
+  const __amdgpu_buffer_rsrc_t rXp = buffer_rsrc(g.X_rowptr, (unsigned)(g.nX + 1) * 4u);
+  const __amdgpu_buffer_rsrc_t rXc = buffer_rsrc(g.X_col, (unsigned)g.nnzX * 4u);
+  const __amdgpu_buffer_rsrc_t rXv = buffer_rsrc(g.X_val, (unsigned)g.nnzX * 8u);
+  const __amdgpu_buffer_rsrc_t rYp = buffer_rsrc(g.Y_rowptr, (unsigned)(g.nY + 1) * 4u);
+  const __amdgpu_buffer_rsrc_t rYc = buffer_rsrc(g.Y_col, (unsigned)g.nnzY * 4u);
+  const __amdgpu_buffer_rsrc_t rYv = buffer_rsrc(g.Y_val, (unsigned)g.nnzY * 8u);
+  const __amdgpu_buffer_rsrc_t rOp = buffer_rsrc(g.O_rowptr, (unsigned)(g.nX + 1) * 4u);
+  const __amdgpu_buffer_rsrc_t rOc = buffer_rsrc(g.O_col, (unsigned)g.nnzO * 4u);
+  wave_sync();
+
+  const int npairs = (count + 1) / 2;
+  const long long gw = (long long)blockIdx.x * kRmWaves + wid;
+  const long long pb0 = gw * pairs_per_wave;
+  const int pb = (int)(pb0 < npairs ? pb0 : npairs);
+  const int pe = (int)(pb + (long long)pairs_per_wave < npairs ? pb + pairs_per_wave : npairs);
+  RmHeader hb{-1, 0, 0, 0, 0};
+  for (int pr = pb; pr < pe; ++pr) {
+    const int k = (pr - pb) % kHalf;
+    if (k == 0) {
+      // headers of the next 32 pairs: lane h*32+k2 loads row 2*(pr+k2)+h
+      const int ri = 2 * (pr + sub) + half;
+      hb = RmHeader{-1, 0, 0, 0, 0};
+      if (pr + sub < pe && ri < count) {
+        hb.r = rows[ri];
+        const v2u xp = ld_pair(rXp, hb.r), op = ld_pair(rOp, hb.r);
+        hb.x0 = (int)xp[0];
+        hb.x1 = (int)xp[1];
+        hb.o0 = (int)op[0];
+        hb.o1 = (int)op[1];
+      }
+    }
+    const RmHeader h = rm_hdr_get(hb, k, half);
+
+    // entries X(r, x0+sub) and the extents of their rows of Y
+    const int t = h.x0 + sub < h.x1 ? h.x0 + sub : -1;
+    const int kc = ld_i32(rXc, t);
+    const double w = ld_dbl(rXv, t);
+    const v2u yp = ld_pair(rYp, t >= 0 ? kc : -1);
+    const int len = (int)yp[1] - (int)yp[0];  // 0 where there is no entry (the load returned 0)
+    const int incl = half_incl_scan(len);
+    const int T0 = __builtin_amdgcn_readlane(incl, kHalf - 1), T1 = __builtin_amdgcn_readlane(incl, WAVE - 1);
+    const int Th = half ? T1 : T0;
+    const unsigned long long nonempty = ballot(len > 0);
+    if (len > 0) {
+      const int rk = prefix_count(nonempty) - (half ? __popc((unsigned)nonempty) : 0);
+      hs->rec[half][rk] = SegRec{w, (int)yp[0] - (incl - len), 0};
+    }
+    wave_sync();
+
+    // the products, 32 per step and half; the first kRmPrefetch steps' gathers go out together
+    const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
+    int before = 0;
+    ProdLoad pq[kRmPrefetch];
+#pragma unroll
+    for (int u = 0; u < kRmPrefetch; ++u)
+      pq[u] = u < nstep ? prod_load(u, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv)
+                        : ProdLoad{0, 0.0, 0.0, false};
+#pragma unroll
+    for (int u = 0; u < kRmPrefetch; ++u)
+      if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
+    for (int st = kRmPrefetch; st < nstep; ++st) {
+      const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv);
+      if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+    }
+    wave_sync();
+
+    // O(r,:) in its stored order
+    const int o = h.o0 + sub < h.o1 ? h.o0 + sub : -1;
+    const int c = ld_i32(rOc, o);
+    if (o >= 0) {
+      unsigned s = hslot(c, kCapShift);
+      int kf = keys[s];
+#pragma unroll 1
+      for (int it = 1; kf != c && kf != EMPTY && it < kCap; ++it) {
+        s = (s + 1) & (kCap - 1);
+        kf = keys[s];
+      }
+      g.O_val[o] = kf == c ? vals[s] : 0.0;
+    }
+    wave_sync();
+    if (Th > 0) {
+      keys[sub] = EMPTY;
+      keys[sub + kHalf] = EMPTY;
+      vals[sub] = 0.0;
+      vals[sub + kHalf] = 0.0;
+    }
+    wave_sync();
+  }
+}
+
+}  // namespace
+
+bool rowmul_short_fits(const RowMulArgs& g) {
+  return g.nnzX * 8 < (1LL << 31) && g.nnzY * 8 < (1LL << 31) && g.nnzO * 4 < (1LL << 31) &&
+         ((long long)g.nX + 1) * 4 < (1LL << 31) && ((long long)g.nY + 1) * 4 < (1LL << 31);
+}
+
+hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, int n_cu,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (!rowmul_short_fits(g)) return hipErrorInvalidValue;
+  // enough wavefronts for every CU to hold its full complement (32), each a contiguous run of
+  // row pairs
+  const long long npairs = ((long long)count + 1) / 2;
+  const long long target = (long long)std::max(n_cu, 1) * 32;
+  const int ppw = (int)std::max<long long>(1, (npairs + target - 1) / target);
+  const long long waves = (npairs + ppw - 1) / ppw;
+  const int grid = (int)((waves + kRmWaves - 1) / kRmWaves);
+  hipLaunchKernelGGL(k_rowmul_short, dim3(grid), dim3(kRmWaves * WAVE),
+                     (size_t)kRmWaves * sizeof(HalfScratch), s, g, rows, count, ppw);
+  return hipGetLastError();
+}
+
+}  // namespace ptapk
