@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="time only the differentiable form (forward + adjoint, for profiler runs)")
+    ap.add_argument("--twostep-only", action="store_true",
+                    help="time only the two-step numeric on the workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of known size (counter calibration) and exit")
     return ap.parse_args()
@@ -150,6 +152,13 @@ def main():
         wall_ms = (time.perf_counter() - t_start) * 1e3 / steps
         per = [e0.elapsed_time(e1) for e0, e1 in evs]
         return wall_ms, float(np.mean(per)), float(np.min(per))
+
+    if args.twostep_only:
+        plan, C, sym_ms, extra = make_plan(algo="twostep")
+        wall_ms, ev_ms, ev_min = time_numeric(plan, C, args.steps, args.warmup)
+        print(json.dumps({"twostep_numeric_ms": round(ev_ms, 4), "symbolic_ms": round(sym_ms, 2),
+                          "peak_extra_mb": round(extra / 2**20, 2)}))
+        return
 
     # ---------------- headline: merged (K = 1) owner fold
     plan, C, sym_ms, extra_aao = make_plan(algo="merged", fold="owner", nblocks=1)

@@ -233,9 +233,11 @@ struct ptap_plan {
   double* PT_val = nullptr;
   long long nnzAP = 0;
   std::vector<RowClass> ap_rows, ptc_rows;
-  int* ap_short = nullptr;   // rows of AP and of C for the short-row kernel (rowmul.hip)
-  int* ptc_short = nullptr;
-  int n_ap_short = 0, n_ptc_short = 0;
+  // rows of AP and of C for the short-row kernel (rowmul.hip): [0] at most 32 entries in the
+  // row of A (of P^T), [1] more
+  int* ap_short[2] = {nullptr, nullptr};
+  int* ptc_short[2] = {nullptr, nullptr};
+  int n_ap_short[2] = {0, 0}, n_ptc_short[2] = {0, 0};
 
   // adjoint
   std::vector<RowClass> bwd_rows;
@@ -570,8 +572,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->AP_val = t.get<double>(P->nnzAP);
     P->PT_val = t.get<double>(P->nnzP);
     // AP rows already classed by exact |R_I|; reclass for maps (value tables have another LDS
-    // limit).  Rows with at most 32 entries in A(I,:) and in AP(I,:) (C(i,:) and P^T(i,:) for
-    // the second product) take the short-row kernel when every array fits its byte range.
+    // limit).  Rows with at most 32 entries in AP(I,:) (in C(i,:) for the second product) take
+    // the short-row kernel when every array fits its byte range.
     for (auto& c : P->ap_rows) t.put(c.rows);
     std::vector<int> hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
     RowMulArgs g1{}, g2{};
@@ -582,44 +584,45 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     g1.nnzO = g2.nnzY = P->nnzAP;
     g2.nnzO = P->nnzC;
     const bool short_ok = rowmul_short_fits(g1) && rowmul_short_fits(g2);
-    std::vector<int> rows, srows;
+    std::vector<int> rows, srows[2];
     std::vector<long long> need;
     for (int I = 0; I < n; ++I)
       if (hr[I] > 0) {
-        if (short_ok && hr[I] <= kRowMulMaxLen && hA_rowptr[I + 1] - hA_rowptr[I] <= kRowMulMaxLen) {
-          srows.push_back(I);
+        if (short_ok && hr[I] <= kRowMulMaxLen) {
+          srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
         } else {
           rows.push_back(I);
           need.push_back(hr[I]);
         }
       }
     P->ap_rows = make_classes(t, rows, need, lmax, s);
-    P->n_ap_short = (int)srows.size();
-    if (!srows.empty()) {
-      P->ap_short = t.get<int>(srows.size());
-      to_device(P->ap_short, srows, s);
-    }
-    std::vector<int> crow, scrow;
+    std::vector<int> crow, scrow[2];
     std::vector<long long> cneed;
     for (int i = 0; i < m; ++i)
       if (h_c_ptr[i + 1] > h_c_ptr[i]) {
-        if (short_ok && h_c_ptr[i + 1] - h_c_ptr[i] <= kRowMulMaxLen &&
-            h_pt_ptr[i + 1] - h_pt_ptr[i] <= kRowMulMaxLen) {
-          scrow.push_back(i);
+        if (short_ok && h_c_ptr[i + 1] - h_c_ptr[i] <= kRowMulMaxLen) {
+          scrow[h_pt_ptr[i + 1] - h_pt_ptr[i] > kHalfLanes].push_back(i);
         } else {
           crow.push_back(i);
           cneed.push_back(h_c_ptr[i + 1] - h_c_ptr[i]);
         }
       }
     P->ptc_rows = make_classes(t, crow, cneed, lmax, s);
-    P->n_ptc_short = (int)scrow.size();
-    if (!scrow.empty()) {
-      P->ptc_short = t.get<int>(scrow.size());
-      to_device(P->ptc_short, scrow, s);
+    for (int k = 0; k < 2; ++k) {
+      P->n_ap_short[k] = (int)srows[k].size();
+      if (!srows[k].empty()) {
+        P->ap_short[k] = t.get<int>(srows[k].size());
+        to_device(P->ap_short[k], srows[k], s);
+      }
+      P->n_ptc_short[k] = (int)scrow[k].size();
+      if (!scrow[k].empty()) {
+        P->ptc_short[k] = t.get<int>(scrow[k].size());
+        to_device(P->ptc_short[k], scrow[k], s);
+      }
     }
     spill_need_ints = std::max(spill_ints(P->ap_rows, 1), spill_ints(P->ptc_rows, 1));
     spill_need_vals = spill_need_ints;
-    P->rows_formed = (int64_t)(rows.size() + srows.size());
+    P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size());
   } else {
     t.put(P->pt_pos);
     P->pt_pos = nullptr;
@@ -902,7 +905,8 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
       const RowMulArgs g1{P->pat.A_rowptr, P->pat.A_col, A_val, P->pat.P_rowptr, P->pat.P_col,
                           P_val, P->AP_rowptr, P->AP_col, P->AP_val, P->pat.n, P->pat.n,
                           P->nnzA, P->nnzP, P->nnzAP};
-      hipck(launch_rowmul_short(g1, P->ap_short, P->n_ap_short, P->n_cu, s));
+      for (int k = 0; k < 2; ++k)
+        hipck(launch_rowmul_short(g1, P->ap_short[k], P->n_ap_short[k], k == 1, P->n_cu, s));
       hipck(launch_gather(P_val, P->pt_pos, P->PT_val, P->nnzP, s));
       for (auto& c : P->ptc_rows)
         hipck(launch_ptc_numeric(P->pt_ptr, P->pt_row, P->PT_val, P->AP_rowptr, P->AP_col,
@@ -910,7 +914,8 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
       const RowMulArgs g2{P->pt_ptr, P->pt_row, P->PT_val, P->AP_rowptr, P->AP_col, P->AP_val,
                           P->C_rowptr, P->C_col, C_val, P->pat.m, P->pat.n,
                           P->nnzP, P->nnzAP, P->nnzC};
-      hipck(launch_rowmul_short(g2, P->ptc_short, P->n_ptc_short, P->n_cu, s));
+      for (int k = 0; k < 2; ++k)
+        hipck(launch_rowmul_short(g2, P->ptc_short[k], P->n_ptc_short[k], k == 1, P->n_cu, s));
       return PTAP_OK;
     }
     const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;

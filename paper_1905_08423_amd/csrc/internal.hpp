@@ -143,7 +143,8 @@ hipError_t launch_ap_numeric(const NumericArgs& a, const RowClass& rc, const int
 hipError_t launch_gather(const double* src, const int* idx, double* dst, long long count,
                          hipStream_t s);
 // Short-row form of both two-step products (rowmul.hip): O(r,:) = sum_k X(r,k) Y(k,:) into O's
-// stored pattern, for rows with at most 32 entries in X(r,:) and in O(r,:).  O has nX rows.
+// stored pattern, for rows with at most 32 entries in O(r,:); long_x: the rows listed may have
+// more than 32 entries in X(r,:).  O has nX rows.
 struct RowMulArgs {
   const int* X_rowptr;
   const int* X_col;
@@ -158,9 +159,10 @@ struct RowMulArgs {
   long long nnzX, nnzY, nnzO;
 };
 constexpr int kRowMulMaxLen = 32;
+constexpr int kHalfLanes = 32;  // entries of X(r,:) one pass of the short-row walk takes
 bool rowmul_short_fits(const RowMulArgs& g);  // byte extents within the 32-bit buffer range
-hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, int n_cu,
-                               hipStream_t s);
+hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                               int n_cu, hipStream_t s);
 hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double* PT_val,
                               const int* AP_rowptr, const int* AP_col, const double* AP_val,
                               const int* C_rowptr, const int* C_col, double* C_val,

@@ -9,9 +9,10 @@
 // kernel: lane `sub` holds X(r, x0+sub) and the extent of row k of Y; the products X(r,k) Y(k,j)
 // are dealt out 32 per step over the half (a prefix sum of the lengths of the rows of Y gives each
 // lane its product and its segment), the gathers of four steps are issued together, and the
-// products are added into the half's 64-slot LDS table.  Then the half reads O's row pattern and
-// writes each value it finds.  Rows with at most 32 entries in X(r,:) and in O(r,:); longer rows
-// take the general kernels.  A wavefront works through a contiguous run of row pairs, whose row
+// products are added into the half's 64-slot LDS table (longer rows of X are taken 32 entries at
+// a time by a second instantiation).
+// Then the half reads O's row pattern and writes each value it finds.  Rows with at most 32
+// entries in O(r,:) (the table's keys); longer rows take the general kernels.  A wavefront works through a contiguous run of row pairs, whose row
 // headers (row, extents in X and in O) lane h*32+k loads for iteration it0+k once per 32
 // iterations.
 #include "internal.hpp"
@@ -38,6 +39,7 @@ __device__ __forceinline__ RmHeader rm_hdr_get(const RmHeader& b, int k, int hal
   return h;
 }
 
+template <bool LONG>
 __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
                                                                   const int* __restrict__ rows,
                                                                   int count, int pairs_per_wave) {
@@ -85,38 +87,49 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
     }
     const RmHeader h = rm_hdr_get(hb, k, half);
 
-    // entries X(r, x0+sub) and the extents of their rows of Y
-    const int t = h.x0 + sub < h.x1 ? h.x0 + sub : -1;
-    const int kc = ld_i32(rXc, t);
-    const double w = ld_dbl(rXv, t);
-    const v2u yp = ld_pair(rYp, t >= 0 ? kc : -1);
-    const int len = (int)yp[1] - (int)yp[0];  // 0 where there is no entry (the load returned 0)
-    const int incl = half_incl_scan(len);
-    const int T0 = __builtin_amdgcn_readlane(incl, kHalf - 1), T1 = __builtin_amdgcn_readlane(incl, WAVE - 1);
-    const int Th = half ? T1 : T0;
-    const unsigned long long nonempty = ballot(len > 0);
-    if (len > 0) {
-      const int rk = prefix_count(nonempty) - (half ? __popc((unsigned)nonempty) : 0);
-      hs->rec[half][rk] = SegRec{w, (int)yp[0] - (incl - len), 0};
-    }
-    wave_sync();
-
-    // the products, 32 per step and half; the first kRmPrefetch steps' gathers go out together
-    const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
-    int before = 0;
-    ProdLoad pq[kRmPrefetch];
+    // X(r,:) 32 entries at a time (one chunk unless LONG): lane sub holds X(r, xb+sub) and the
+    // extent of its row of Y; the chunk's products, 32 per step and half, go into the table (the
+    // first kRmPrefetch steps' gathers are issued together)
+    const int xl = h.x1 - h.x0;
+    auto chunk = [&](int xb) {
+      const int t = xb + sub < xl ? h.x0 + xb + sub : -1;
+      const int kc = ld_i32(rXc, t);
+      const double w = ld_dbl(rXv, t);
+      const v2u yp = ld_pair(rYp, t >= 0 ? kc : -1);
+      const int len = (int)yp[1] - (int)yp[0];  // 0 where there is no entry (the load returned 0)
+      const int incl = half_incl_scan(len);
+      const int T0 = __builtin_amdgcn_readlane(incl, kHalf - 1), T1 = __builtin_amdgcn_readlane(incl, WAVE - 1);
+      const int Th = half ? T1 : T0;
+      const unsigned long long nonempty = ballot(len > 0);
+      if (len > 0) {
+        const int rk = prefix_count(nonempty) - (half ? __popc((unsigned)nonempty) : 0);
+        hs->rec[half][rk] = SegRec{w, (int)yp[0] - (incl - len), 0};
+      }
+      wave_sync();
+      const int nstep = (max(T0, T1) + kHalf - 1) / kHalf;
+      int before = 0;
+      ProdLoad pq[kRmPrefetch];
 #pragma unroll
-    for (int u = 0; u < kRmPrefetch; ++u)
-      pq[u] = u < nstep ? prod_load(u, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv)
-                        : ProdLoad{0, 0.0, 0.0, false};
+      for (int u = 0; u < kRmPrefetch; ++u)
+        pq[u] = u < nstep ? prod_load(u, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv)
+                          : ProdLoad{0, 0.0, 0.0, false};
 #pragma unroll
-    for (int u = 0; u < kRmPrefetch; ++u)
-      if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
-    for (int st = kRmPrefetch; st < nstep; ++st) {
-      const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv);
-      if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+      for (int u = 0; u < kRmPrefetch; ++u)
+        if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
+      for (int st = kRmPrefetch; st < nstep; ++st) {
+        const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rYc, rYv);
+        if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+      }
+      wave_sync();
+    };
+    if constexpr (LONG) {
+      // a loop around the walk costs the one-chunk rows about half their speed (measured), so
+      // rows with at most 32 entries in X(r,:) use the other instantiation
+      const int xlmax = max(__builtin_amdgcn_readlane(xl, 0), __builtin_amdgcn_readlane(xl, kHalf));
+      for (int xb = 0; xb < xlmax; xb += kHalf) chunk(xb);
+    } else {
+      chunk(0);
     }
-    wave_sync();
 
     // O(r,:) in its stored order
     const int o = h.o0 + sub < h.o1 ? h.o0 + sub : -1;
@@ -132,7 +145,7 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
       g.O_val[o] = kf == c ? vals[s] : 0.0;
     }
     wave_sync();
-    if (Th > 0) {
+    if (h.o1 > h.o0) {
       keys[sub] = EMPTY;
       keys[sub + kHalf] = EMPTY;
       vals[sub] = 0.0;
@@ -149,8 +162,8 @@ bool rowmul_short_fits(const RowMulArgs& g) {
          ((long long)g.nX + 1) * 4 < (1LL << 31) && ((long long)g.nY + 1) * 4 < (1LL << 31);
 }
 
-hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, int n_cu,
-                               hipStream_t s) {
+hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                               int n_cu, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (!rowmul_short_fits(g)) return hipErrorInvalidValue;
   // enough wavefronts for every CU to hold its full complement (32), each a contiguous run of
@@ -160,8 +173,13 @@ hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, 
   const int ppw = (int)std::max<long long>(1, (npairs + target - 1) / target);
   const long long waves = (npairs + ppw - 1) / ppw;
   const int grid = (int)((waves + kRmWaves - 1) / kRmWaves);
-  hipLaunchKernelGGL(k_rowmul_short, dim3(grid), dim3(kRmWaves * WAVE),
-                     (size_t)kRmWaves * sizeof(HalfScratch), s, g, rows, count, ppw);
+  const size_t lds = (size_t)kRmWaves * sizeof(HalfScratch);
+  if (long_x)
+    hipLaunchKernelGGL(k_rowmul_short<true>, dim3(grid), dim3(kRmWaves * WAVE), lds, s, g, rows,
+                       count, ppw);
+  else
+    hipLaunchKernelGGL(k_rowmul_short<false>, dim3(grid), dim3(kRmWaves * WAVE), lds, s, g, rows,
+                       count, ppw);
   return hipGetLastError();
 }
 
