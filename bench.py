@@ -37,8 +37,8 @@ def algorithmic_bytes(n, nnzA, nnzP, nnzC):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "owner_numeric_128cubed_27pt.md")
-KERNEL_SOURCES = ["paper_1905_08423_amd/csrc/owner.hip", "paper_1905_08423_amd/csrc/device.hpp",
-                  "paper_1905_08423_amd/csrc/internal.hpp"]
+KERNEL_SOURCES = ["paper_1905_08423_amd/csrc/owner.hip", "paper_1905_08423_amd/csrc/short_rows.hpp",
+                  "paper_1905_08423_amd/csrc/device.hpp", "paper_1905_08423_amd/csrc/internal.hpp"]
 
 
 def profiled_traffic():
