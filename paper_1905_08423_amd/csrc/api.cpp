@@ -728,6 +728,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->host_fptr = fptr;
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, s));
+      hipck(launch_tile_order(pat, P->tile_fptr, T, P->tile_fine, P->tile_slot, s));
       P->rows_formed = acc;
       // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
       // its (empty) rows are written
