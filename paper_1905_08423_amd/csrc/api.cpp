@@ -223,8 +223,11 @@ struct ptap_plan {
   std::vector<TileClass> tclasses;
   bool any_tile_global = false;
 
-  // atomic fold
+  // atomic fold: general row classes and the short-row lists ([0] at most 32 entries in A(I,:),
+  // [1] more)
   std::vector<RowClass> arows;
+  int* af_short[2] = {nullptr, nullptr};
+  int n_af_short[2] = {0, 0};
 
   // two-step
   int* AP_rowptr = nullptr;
@@ -629,18 +632,47 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     const bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
     P->fold_used = atomic ? PTAP_FOLD_ATOMIC : PTAP_FOLD_OWNER;
     if (atomic) {
-      std::vector<int> rows;
+      // Single-pass forms: rows with |R_I| <= 32, at most 32 entries in P(I,:) and at most 32 in
+      // every row of C under them take the short-row kernel; the others the general one.
+      const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+      RowMulArgs gf{};
+      gf.nX = gf.nY = n;
+      gf.nnzX = P->nnzA;
+      gf.nnzY = gf.nnzO = P->nnzP;
+      gf.nF = m;
+      gf.nnzF = P->nnzC;
+      const bool short_ok = !twopass && rowmul_short_fits(gf);
+      std::vector<int> hA_rowptr, hPc;
+      if (short_ok) {
+        hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
+        hPc = to_host(pat.P_col, (size_t)P->nnzP, s);
+      }
+      std::vector<int> rows, srows[2];
       std::vector<long long> need;
       for (int I = 0; I < n; ++I)
         if (hP_rowptr[I + 1] > hP_rowptr[I] && hr[I] > 0) {
-          rows.push_back(I);
-          need.push_back(hr[I]);
+          bool fits = short_ok && hr[I] <= kRowMulMaxLen &&
+                      hP_rowptr[I + 1] - hP_rowptr[I] <= kRowMulMaxLen;
+          for (int e = hP_rowptr[I]; fits && e < hP_rowptr[I + 1]; ++e)
+            fits = h_c_ptr[hPc[e] + 1] - h_c_ptr[hPc[e]] <= kRowMulMaxLen;
+          if (fits) {
+            srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
+          } else {
+            rows.push_back(I);
+            need.push_back(hr[I]);
+          }
         }
       P->arows = make_classes(t, rows, need, lmax, s);
+      for (int k = 0; k < 2; ++k) {
+        P->n_af_short[k] = (int)srows[k].size();
+        if (!srows[k].empty()) {
+          P->af_short[k] = t.get<int>(srows[k].size());
+          to_device(P->af_short[k], srows[k], s);
+        }
+      }
       spill_need_ints = spill_ints(P->arows, 1);
       spill_need_vals = spill_need_ints;
-      const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
-      P->rows_formed = (int64_t)rows.size() * (twopass ? 2 : 1);  // upper bound for two passes
+      P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size()) * (twopass ? 2 : 1);
       t.put(P->pt_ptr);
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
@@ -927,6 +959,11 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
         NumericArgs a = numeric_args(P, A_val, P_val, C_val, parts[k]);
         for (auto& c : P->arows) hipck(launch_atomic_numeric(a, c, P->gtab, P->gval, s));
       }
+      RowMulArgs gf{P->pat.A_rowptr, P->pat.A_col, A_val, P->pat.P_rowptr, P->pat.P_col, P_val,
+                    P->pat.P_rowptr, P->pat.P_col, nullptr, P->pat.n, P->pat.n, P->nnzA,
+                    P->nnzP, P->nnzP, P_val, P->C_rowptr, P->C_col, C_val, P->pat.m, P->nnzC};
+      for (int k = 0; k < 2; ++k)
+        hipck(launch_atomic_fold_short(gf, P->af_short[k], P->n_af_short[k], k == 1, P->n_cu, s));
       return PTAP_OK;
     }
     if (P->any_tile_global) hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));

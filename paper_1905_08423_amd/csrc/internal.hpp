@@ -160,12 +160,24 @@ struct RowMulArgs {
   double* O_val;
   int nX, nY;
   long long nnzX, nnzY, nnzO;
+  // atomic fold only: O_rowptr / O_col are P's (the entries P(I,i) folded), F_val P's values,
+  // and C += P(I,:) (x) R_I goes into F_out on C's pattern (F_rowptr, F_col; nF rows, nnzF entries)
+  const double* F_val;
+  const int* F_rowptr;
+  const int* F_col;
+  double* F_out;
+  int nF;
+  long long nnzF;
 };
 constexpr int kRowMulMaxLen = 32;
 constexpr int kHalfLanes = 32;  // entries of X(r,:) one pass of the short-row walk takes
 bool rowmul_short_fits(const RowMulArgs& g);  // byte extents within the 32-bit buffer range
 hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
                                int n_cu, hipStream_t s);
+// Short-row atomic fold (F1): X = A, Y = P; rows I with |R_I| <= 32, at most 32 entries in
+// P(I,:) and at most 32 in each row of C under them.  C must be zeroed first.
+hipError_t launch_atomic_fold_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                                    int n_cu, hipStream_t s);
 hipError_t launch_ptc_numeric(const int* pt_ptr, const int* pt_row, const double* PT_val,
                               const int* AP_rowptr, const int* AP_col, const double* AP_val,
                               const int* C_rowptr, const int* C_col, double* C_val,

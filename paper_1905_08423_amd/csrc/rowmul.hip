@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kRmWaves = 8;
 constexpr int kRmPrefetch = 4;  // product-walk steps whose loads are issued together
+constexpr int kFoldBatch = 4;   // atomic fold: entries of P(I,:) whose columns are loaded together
 
 struct RmHeader {
   int r, x0, x1, o0, o1;  // row of O (or -1), its extents in X and in O
@@ -39,7 +40,7 @@ __device__ __forceinline__ RmHeader rm_hdr_get(const RmHeader& b, int k, int hal
   return h;
 }
 
-template <bool LONG>
+template <bool LONG, bool FOLD>
 __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
                                                                   const int* __restrict__ rows,
                                                                   int count, int pairs_per_wave) {
@@ -62,6 +63,9 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
   const __amdgpu_buffer_rsrc_t rYv = buffer_rsrc(g.Y_val, (unsigned)g.nnzY * 8u);
   const __amdgpu_buffer_rsrc_t rOp = buffer_rsrc(g.O_rowptr, (unsigned)(g.nX + 1) * 4u);
   const __amdgpu_buffer_rsrc_t rOc = buffer_rsrc(g.O_col, (unsigned)g.nnzO * 4u);
+  const __amdgpu_buffer_rsrc_t rFv = buffer_rsrc(g.F_val, FOLD ? (unsigned)g.nnzO * 8u : 0u);
+  const __amdgpu_buffer_rsrc_t rFp = buffer_rsrc(g.F_rowptr, FOLD ? (unsigned)(g.nF + 1) * 4u : 0u);
+  const __amdgpu_buffer_rsrc_t rFc = buffer_rsrc(g.F_col, FOLD ? (unsigned)g.nnzF * 4u : 0u);
   wave_sync();
 
   const int npairs = (count + 1) / 2;
@@ -131,18 +135,60 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
       chunk(0);
     }
 
-    // O(r,:) in its stored order
-    const int o = h.o0 + sub < h.o1 ? h.o0 + sub : -1;
-    const int c = ld_i32(rOc, o);
-    if (o >= 0) {
-      unsigned s = hslot(c, kCapShift);
-      int kf = keys[s];
+    if constexpr (FOLD) {
+      // the atomic fold: C(i,:) += P(I,i) R_I for every entry P(I,i) (O's row r = P(I,:)); lane
+      // sub holds entry sub's weight and the extent of row i of C, and each step takes kFoldBatch
+      // entries of both halves: their column loads go out together, then every lane of a half
+      // looks its column up in R_I and adds into C with a device-wide FP64 atomic
+      const int npi = h.o1 - h.o0;
+      const int e = sub < npi ? h.o0 + sub : -1;
+      const int ci = ld_i32(rOc, e);
+      const double cw = ld_dbl(rFv, e);
+      const v2u cp = ld_pair(rFp, e >= 0 ? ci : -1);
+      const int cc0 = (int)cp[0], cc1 = (int)cp[1];
+      const long long cwb = __double_as_longlong(cw);
+      const int cwl = (int)cwb, cwh = (int)(cwb >> 32);
+      const int nmax = max(__builtin_amdgcn_readlane(npi, 0), __builtin_amdgcn_readlane(npi, kHalf));
+      for (int kb = 0; kb < nmax; kb += kFoldBatch) {
+        int cix[kFoldBatch], jj[kFoldBatch];
+        double ww[kFoldBatch];
+#pragma unroll
+        for (int u = 0; u < kFoldBatch; ++u) {
+          const int kk = kb + u < kHalf ? kb + u : kHalf - 1;
+          const int src = (half * kHalf + kk) * 4;
+          const int c0 = __builtin_amdgcn_ds_bpermute(src, cc0), c1 = __builtin_amdgcn_ds_bpermute(src, cc1);
+          const int wl = __builtin_amdgcn_ds_bpermute(src, cwl), wh = __builtin_amdgcn_ds_bpermute(src, cwh);
+          ww[u] = __longlong_as_double(((long long)wh << 32) | (unsigned)wl);
+          cix[u] = kb + u < nmax && c0 + sub < c1 ? c0 + sub : -1;  // rows of C have <= 32 entries
+          jj[u] = ld_i32(rFc, cix[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kFoldBatch; ++u)
+          if (cix[u] >= 0) {
+            unsigned s = hslot(jj[u], kCapShift);
+            int kf = keys[s];
 #pragma unroll 1
-      for (int it = 1; kf != c && kf != EMPTY && it < kCap; ++it) {
-        s = (s + 1) & (kCap - 1);
-        kf = keys[s];
+            for (int it = 1; kf != jj[u] && kf != EMPTY && it < kCap; ++it) {
+              s = (s + 1) & (kCap - 1);
+              kf = keys[s];
+            }
+            if (kf == jj[u]) unsafeAtomicAdd(g.F_out + cix[u], ww[u] * vals[s]);
+          }
       }
-      g.O_val[o] = kf == c ? vals[s] : 0.0;
+    } else {
+      // O(r,:) in its stored order
+      const int o = h.o0 + sub < h.o1 ? h.o0 + sub : -1;
+      const int c = ld_i32(rOc, o);
+      if (o >= 0) {
+        unsigned s = hslot(c, kCapShift);
+        int kf = keys[s];
+#pragma unroll 1
+        for (int it = 1; kf != c && kf != EMPTY && it < kCap; ++it) {
+          s = (s + 1) & (kCap - 1);
+          kf = keys[s];
+        }
+        g.O_val[o] = kf == c ? vals[s] : 0.0;
+      }
     }
     wave_sync();
     if (h.o1 > h.o0) {
@@ -158,12 +204,13 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
 }  // namespace
 
 bool rowmul_short_fits(const RowMulArgs& g) {
-  return g.nnzX * 8 < (1LL << 31) && g.nnzY * 8 < (1LL << 31) && g.nnzO * 4 < (1LL << 31) &&
-         ((long long)g.nX + 1) * 4 < (1LL << 31) && ((long long)g.nY + 1) * 4 < (1LL << 31);
+  return g.nnzX * 8 < (1LL << 31) && g.nnzY * 8 < (1LL << 31) && g.nnzO * 8 < (1LL << 31) &&
+         ((long long)g.nX + 1) * 4 < (1LL << 31) && ((long long)g.nY + 1) * 4 < (1LL << 31) &&
+         g.nnzF * 4 < (1LL << 31) && ((long long)g.nF + 1) * 4 < (1LL << 31);
 }
 
-hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
-                               int n_cu, hipStream_t s) {
+static hipError_t launch_rowmul(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                                bool fold, int n_cu, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   if (!rowmul_short_fits(g)) return hipErrorInvalidValue;
   // enough wavefronts for every CU to hold its full complement (32), each a contiguous run of
@@ -174,13 +221,29 @@ hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, 
   const long long waves = (npairs + ppw - 1) / ppw;
   const int grid = (int)((waves + kRmWaves - 1) / kRmWaves);
   const size_t lds = (size_t)kRmWaves * sizeof(HalfScratch);
-  if (long_x)
-    hipLaunchKernelGGL(k_rowmul_short<true>, dim3(grid), dim3(kRmWaves * WAVE), lds, s, g, rows,
-                       count, ppw);
-  else
-    hipLaunchKernelGGL(k_rowmul_short<false>, dim3(grid), dim3(kRmWaves * WAVE), lds, s, g, rows,
-                       count, ppw);
+  const dim3 gd(grid), bd(kRmWaves * WAVE);
+  if (fold) {
+    if (long_x)
+      hipLaunchKernelGGL((k_rowmul_short<true, true>), gd, bd, lds, s, g, rows, count, ppw);
+    else
+      hipLaunchKernelGGL((k_rowmul_short<false, true>), gd, bd, lds, s, g, rows, count, ppw);
+  } else {
+    if (long_x)
+      hipLaunchKernelGGL((k_rowmul_short<true, false>), gd, bd, lds, s, g, rows, count, ppw);
+    else
+      hipLaunchKernelGGL((k_rowmul_short<false, false>), gd, bd, lds, s, g, rows, count, ppw);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_rowmul_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                               int n_cu, hipStream_t s) {
+  return launch_rowmul(g, rows, count, long_x, false, n_cu, s);
+}
+
+hipError_t launch_atomic_fold_short(const RowMulArgs& g, const int* rows, int count, bool long_x,
+                                    int n_cu, hipStream_t s) {
+  return launch_rowmul(g, rows, count, long_x, true, n_cu, s);
 }
 
 }  // namespace ptapk
