@@ -1,20 +1,22 @@
-// Row-times-matrix products into a known output pattern, short-row form: the two numeric
-// products of the two-step method (Alg. 6),
+// Row-times-matrix products, short-row form.  In product mode, the two numeric products of the
+// two-step method (Alg. 6), each row O(r,:) = sum_k X(r,k) Y(k,:) written into O's stored,
+// sorted pattern:
 //   AP = A P          X = A,    Y = P,   O = AP   (the stored auxiliary matrix, Alg. 4 rows)
 //   C  = P^T (AP)     X = P^T,  Y = AP,  O = C    (rows of P^T: the column lists of P with the
 //                                                  gathered values of its entries)
-// each row O(r,:) = sum_k X(r,k) Y(k,:) written into O's stored, sorted pattern.
+// In fold mode, the all-at-once product with the atomic fold: X = A, Y = P give R_I, and
+// C(i,:) += P(I,i) R_I for every entry of P(I,:) (Eq. allatonceoutproduct) with device FP64
+// atomics on C's pattern.
 //
 // Two rows per wavefront, one per 32-lane half, in the manner of the owner fold's short-row
 // kernel: lane `sub` holds X(r, x0+sub) and the extent of row k of Y; the products X(r,k) Y(k,j)
 // are dealt out 32 per step over the half (a prefix sum of the lengths of the rows of Y gives each
 // lane its product and its segment), the gathers of four steps are issued together, and the
 // products are added into the half's 64-slot LDS table (longer rows of X are taken 32 entries at
-// a time by a second instantiation).
-// Then the half reads O's row pattern and writes each value it finds.  Rows with at most 32
-// entries in O(r,:) (the table's keys); longer rows take the general kernels.  A wavefront works through a contiguous run of row pairs, whose row
-// headers (row, extents in X and in O) lane h*32+k loads for iteration it0+k once per 32
-// iterations.
+// a time by a second instantiation).  Then the half writes O's row (product mode) or folds (fold
+// mode).  Rows with at most 32 keys; longer rows take the general kernels.  A wavefront works
+// through a contiguous run of row pairs, whose row headers (row, extents in X and in O) lane
+// h*32+k loads for iteration it0+k once per 32 iterations.
 #include "internal.hpp"
 #include "short_rows.hpp"
 
