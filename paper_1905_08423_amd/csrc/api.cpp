@@ -760,7 +760,6 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->host_fptr = fptr;
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, s));
-      hipck(launch_tile_order(pat, P->tile_fptr, T, P->tile_fine, P->tile_slot, s));
       P->rows_formed = acc;
       // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
       // its (empty) rows are written
@@ -786,6 +785,9 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         tc.tiles = t.get<int>(tc.count);
         to_device(tc.tiles, kv.second, s);
         tc.host_tiles = kv.second;
+        // the short-row kernel pairs consecutive rows of a tile's list: order them by owned count
+        if (tc.fast)
+          hipck(launch_tile_order(pat, tc.tiles, tc.count, P->tile_fptr, P->tile_fine, P->tile_slot, s));
         if (tc.tile_global) P->any_tile_global = true;
         if (tc.hash_global)
           spill_need_ints = std::max(spill_need_ints, (size_t)tc.count * kWavesPerBlock * tc.cap);

@@ -77,9 +77,10 @@ hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row
 hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
                             const TileSet& ts, int ntiles, const int* r, bool fill, int* cnt_out,
                             int* rmax_out, const int* fptr, int* fine, hipStream_t s);
-// Reorder each tile's list (in place) by the count of the row's entries of P the tile owns.
-hipError_t launch_tile_order(const Patterns& p, const int* fptr, int ntiles, int* fine,
-                             const int* slot, hipStream_t s);
+// Reorder the lists of the given tiles (in place) by the count of the row's entries of P the
+// tile owns.
+hipError_t launch_tile_order(const Patterns& p, const int* tiles, int ntiles, const int* fptr,
+                             int* fine, const int* slot, hipStream_t s);
 
 struct NumericArgs {
   Patterns p;

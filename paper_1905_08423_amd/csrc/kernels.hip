@@ -457,47 +457,60 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
   }
 }
 
-// Order each tile's fine-row list, within windows of 64 consecutive rows, by the number of the
-// row's entries of P that the tile owns (ascending, rows of equal count in ascending index order):
-// the short-row owner kernel pairs consecutive rows in a wavefront and its fold takes as many
-// steps as the larger of the two counts.  Short windows keep neighbouring rows together, so the
-// tile is still swept once and rows close in the list share A's and P's rows in the caches
-// (ordering whole tiles doubled the kernel's HBM traffic).  One wavefront per window: a stable
-// counting sort by ballots.
+// Order each tile's fine-row list by the number of the row's entries of P that the tile owns
+// (ascending, rows of equal count in ascending index order): the short-row owner kernel pairs
+// consecutive rows in a wavefront and its fold takes as many steps as the larger of the two
+// counts.  One workgroup per tile, a stable counting sort in LDS; lists longer than kOrderMax
+// keep their ascending order.  (The order costs cache locality: at 128^3 the kernel fetches 2.8
+// instead of 1.5 GB per launch, and is still faster; ordering within windows of 64 or 256
+// consecutive rows kept more locality but paired worse, and was slower where P(I,:) has many
+// different lengths.)
+constexpr int kOrderMax = 8192;
 constexpr int kOrderKeys = 64;
-__global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict__ fptr, int* fine,
+__global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict__ tiles,
+                                                           const int* __restrict__ fptr, int* fine,
                                                            const int* __restrict__ P_rowptr,
                                                            const int* __restrict__ P_col,
                                                            const int* __restrict__ slot) {
-  const int tile = blockIdx.x;
-  const int wid = threadIdx.x / WAVE, ln = lane();
+  __shared__ int rows_l[kOrderMax];
+  __shared__ unsigned char key_l[kOrderMax];
+  __shared__ int hist[kOrderKeys];
+  __shared__ int red[kTileBlock / WAVE];
+  const int tile = tiles[blockIdx.x];
   const int f0 = fptr[tile], nf = fptr[tile + 1] - f0;
-  for (int base = wid * WAVE; base < nf; base += kTileBlock) {
-    const int q = base + ln;
-    int I = -1, k = kOrderKeys;  // lanes past the list take no key
-    if (q < nf) {
-      I = fine[f0 + q];
-      int own = 0;
-      for (int e = P_rowptr[I]; e < P_rowptr[I + 1]; ++e)
-        own += (slot[P_col[e]] >> kTileRowBits) == tile ? 1 : 0;
-      k = min(own, kOrderKeys - 1);
-    }
-    // every lane has read its row (the ballots below use it) before any is written back
-    int written = 0;
-    for (int v = 0; v < kOrderKeys; ++v) {
-      const unsigned long long m = ballot(k == v);
-      if (m == 0) continue;
-      if (k == v) fine[f0 + base + written + prefix_count(m)] = I;
-      written += __popcll(m);
+  if (nf < 2 || nf > kOrderMax) return;
+  if (threadIdx.x < kOrderKeys) hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nf; q += kTileBlock) {
+    const int I = fine[f0 + q];
+    int own = 0;
+    for (int e = P_rowptr[I]; e < P_rowptr[I + 1]; ++e)
+      own += (slot[P_col[e]] >> kTileRowBits) == tile ? 1 : 0;
+    const int k = min(own, kOrderKeys - 1);
+    rows_l[q] = I;
+    key_l[q] = (unsigned char)k;
+    atomicAdd(hist + k, 1);
+  }
+  __syncthreads();
+  int written = 0;
+  for (int v = 0; v < kOrderKeys; ++v) {
+    if (hist[v] == 0) continue;  // the same for every thread
+    for (int base = 0; base < nf; base += kTileBlock) {
+      const int q = base + threadIdx.x;
+      const bool take = q < nf && key_l[q] == v;
+      int total;
+      const int pos = block_excl_scan(take ? 1 : 0, red, total);
+      if (take) fine[f0 + written + pos] = rows_l[q];
+      written += total;
     }
   }
 }
 
-hipError_t launch_tile_order(const Patterns& p, const int* fptr, int ntiles, int* fine,
-                             const int* slot, hipStream_t s) {
+hipError_t launch_tile_order(const Patterns& p, const int* tiles, int ntiles, const int* fptr,
+                             int* fine, const int* slot, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile_order, dim3(ntiles), dim3(kTileBlock), 0, s, fptr, fine, p.P_rowptr,
-                     p.P_col, slot);
+  hipLaunchKernelGGL(k_tile_order, dim3(ntiles), dim3(kTileBlock), 0, s, tiles, fptr, fine,
+                     p.P_rowptr, p.P_col, slot);
   return hipGetLastError();
 }
 
