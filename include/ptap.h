@@ -234,6 +234,16 @@ const char* ptap_status_string(ptap_status status);
 /* The hipError_t of the last failing HIP call made by the library on this thread (0 if none). */
 int32_t ptap_last_hip_error(void);
 
+/*
+ * Measurement helper, not part of the product: *out = sum of x[0..n), a plain streaming read of
+ * n FP64 values (every value read once, in coalesced 16-byte loads).  Timing it gives the HBM
+ * read bandwidth this device reaches, the measured counterpart of the published peak that the
+ * numeric kernels are compared against.  x and out are device pointers; x holds n values and
+ * must be 16-byte aligned; out is overwritten.  Asynchronous on stream.
+ * Errors: PTAP_ERR_INPUT (NULL pointer with n > 0, n < 0, misaligned x), PTAP_ERR_HIP.
+ */
+ptap_status ptap_stream_sum(const double* x, int64_t n, double* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,6 +84,7 @@ _SIGNATURES = {
     "ptap_batch_destroy": (None, [_vp]),
     "ptap_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ptap_last_hip_error": (_i32, []),
+    "ptap_stream_sum": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
 }
 
 _lib = None
@@ -226,6 +227,15 @@ def ptap_status_string(status):
 
 def ptap_last_hip_error():
     return load_library().ptap_last_hip_error()
+
+
+def stream_sum(x, out=None, stream=None):
+    """Sum of the FP64 tensor x by the library's streaming-read kernel (a bandwidth probe)."""
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(load_library().ptap_stream_sum(_ptr(x), int(x.numel()), _ptr(out), _stream(stream)),
+           "ptap_stream_sum")
+    return out
 
 
 # ---------------------------------------------------------------------------------------------

@@ -317,6 +317,16 @@ const char* ptap_status_string(ptap_status s) {
 
 int32_t ptap_last_hip_error(void) { return g_last_hip_error; }
 
+ptap_status ptap_stream_sum(const double* x, int64_t n, double* out, hipStream_t s) {
+  if (n < 0 || !out || (n > 0 && !x) || ((uintptr_t)x & 15u)) return PTAP_ERR_INPUT;
+  try {
+    hipck(launch_stream_sum(x, n, out, s));
+  } catch (const Failure& f) {
+    return f.status;
+  }
+  return PTAP_OK;
+}
+
 ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_t* A_rowptr,
                              const int32_t* A_col, int64_t A_nnz, const int32_t* P_rowptr,
                              const int32_t* P_col, int64_t P_nnz, const ptap_options* opts,

@@ -58,6 +58,7 @@ hipError_t launch_validate(const int* rowptr, const int* col, int nrows, int nco
                            int* err, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int value, long long count, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double value, long long count, hipStream_t s);
+hipError_t launch_stream_sum(const double* x, long long n, double* out, hipStream_t s);
 hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_t s);
 hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
                                  int* t_row, int* t_pos, hipStream_t s);

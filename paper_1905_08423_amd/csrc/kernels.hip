@@ -74,6 +74,38 @@ hipError_t launch_fill_i32(int* p, int value, long long count, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Streaming read: every thread sums its 16-byte pairs in grid-stride order, then the wavefront
+// and the workgroup reduce, and one device-wide add per workgroup goes into *out (zeroed first).
+__global__ __launch_bounds__(256) void k_stream_sum(const double2* __restrict__ x, long long npairs,
+                                                    const double* __restrict__ tail, int ntail,
+                                                    double* out) {
+  __shared__ double red[256 / WAVE];
+  double acc = 0.0;
+  for (long long k = blockIdx.x * 256LL + threadIdx.x; k < npairs; k += (long long)gridDim.x * 256) {
+    const double2 v = x[k];
+    acc += v.x + v.y;
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) acc += tail[threadIdx.x];
+  acc = wave_sum(acc);
+  if (lane() == 0) red[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) t += red[w];
+    atomicAdd(out, t);
+  }
+}
+
+hipError_t launch_stream_sum(const double* x, long long n, double* out, hipStream_t s) {
+  hipError_t e = launch_fill_f64(out, 0.0, 1, s);
+  if (e != hipSuccess || n <= 0) return e;
+  const long long npairs = n / 2;
+  hipLaunchKernelGGL(k_stream_sum, dim3(grid_for(npairs, 256, 8192)), dim3(256), 0, s,
+                     reinterpret_cast<const double2*>(x), npairs, x + 2 * npairs, (int)(n - 2 * npairs),
+                     out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(double* p, double value, long long count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, value,

@@ -132,3 +132,24 @@ def test_allocator_failure_reports_oom():
     lib.ptap_plan_destroy(h)
     torch.cuda.synchronize()
     del keep
+
+
+def test_stream_sum_arguments_rejected_without_gpu():
+    f = lib.load_library().ptap_stream_sum
+    assert f(None, 4, None, None) == lib.PTAP_ERR_INPUT
+    assert f(None, -1, None, None) == lib.PTAP_ERR_INPUT
+
+
+@gpu
+@pytest.mark.parametrize("n", [0, 1, 7, 1 << 20, (1 << 22) + 3])
+def test_stream_sum_matches_the_sum(n):
+    """The bandwidth probe reads every value once: its sum equals numpy's within the rounding of
+    two summation orders (|error| <= n * eps * sum |x|)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    x = np.random.default_rng(n).uniform(-1.0, 1.0, n)
+    got = float(lib.stream_sum(torch.as_tensor(x).cuda()).item())
+    bound = max(n, 1) * 2.3e-16 * float(np.abs(x).sum())
+    assert abs(got - float(x.sum())) <= bound
+    odd = torch.as_tensor(np.zeros(3)).cuda()[1:]  # 8-byte aligned view
+    assert lib.load_library().ptap_stream_sum(lib._ptr(odd), 2, lib._ptr(odd), None) == lib.PTAP_ERR_INPUT
