@@ -493,12 +493,13 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
 // (ascending, rows of equal count in ascending index order): the short-row owner kernel pairs
 // consecutive rows in a wavefront and its fold takes as many steps as the larger of the two
 // counts.  One workgroup per tile, a stable counting sort in LDS; lists longer than kOrderMax
-// keep their ascending order.  (The order costs cache locality: at 128^3 the kernel fetches 2.8
-// instead of 1.5 GB per launch, and is still faster; ordering within windows of 64 or 256
-// consecutive rows kept more locality but paired worse, and was slower where P(I,:) has many
-// different lengths.)
+// keep their ascending order.  The order costs cache locality (rows of P are fetched again
+// between the sweeps of the count classes), so a tile with few distinct counts is ordered within
+// windows of kTileBlock consecutive rows, which pairs as well there; a tile with many (rows of P
+// of many lengths) is ordered as a whole, since windows pair badly there.
 constexpr int kOrderMax = 8192;
 constexpr int kOrderKeys = 64;
+constexpr int kOrderFewKeys = 8;
 __global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict__ tiles,
                                                            const int* __restrict__ fptr, int* fine,
                                                            const int* __restrict__ P_rowptr,
@@ -524,16 +525,25 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict
     atomicAdd(hist + k, 1);
   }
   __syncthreads();
-  int written = 0;
-  for (int v = 0; v < kOrderKeys; ++v) {
-    if (hist[v] == 0) continue;  // the same for every thread
-    for (int base = 0; base < nf; base += kTileBlock) {
-      const int q = base + threadIdx.x;
-      const bool take = q < nf && key_l[q] == v;
-      int total;
-      const int pos = block_excl_scan(take ? 1 : 0, red, total);
-      if (take) fine[f0 + written + pos] = rows_l[q];
-      written += total;
+  // With few distinct counts, windows of kTileBlock consecutive rows already pair like with like
+  // and keep neighbouring rows together (less re-fetching between sweeps); otherwise the whole
+  // tile is one window.
+  int nbins = 0;
+  for (int v = 0; v < kOrderKeys; ++v) nbins += hist[v] > 0 ? 1 : 0;
+  const int win = nbins <= kOrderFewKeys ? kTileBlock : nf;
+  for (int w0 = 0; w0 < nf; w0 += win) {
+    const int w1 = min(w0 + win, nf);
+    int written = 0;
+    for (int v = 0; v < kOrderKeys; ++v) {
+      if (hist[v] == 0) continue;  // the same for every thread
+      for (int base = w0; base < w1; base += kTileBlock) {
+        const int q = base + threadIdx.x;
+        const bool take = q < w1 && key_l[q] == v;
+        int total;
+        const int pos = block_excl_scan(take ? 1 : 0, red, total);
+        if (take) fine[f0 + w0 + written + pos] = rows_l[q];
+        written += total;
+      }
     }
   }
 }
