@@ -227,14 +227,8 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
           const int c0 = kk < nsel ? rc.base : 0, c1 = kk < nsel ? rc.pad : 0;
           for (int c = c0 + sub; c < c1; c += kHalf) {
             const int j = tc[c];
-            unsigned s = hslot(j, kCapShift);
-            int kf = keys[s];
-#pragma unroll 1
-            for (int it = 1; kf != j && kf != EMPTY && it < kCap; ++it) {
-              s = (s + 1) & (kCap - 1);
-              kf = keys[s];
-            }
-            if (kf == j) atomicAdd(tv + c, rc.w * vals[s]);
+            const int s = hash_find64(keys, j);
+            if (s >= 0) atomicAdd(tv + c, rc.w * vals[s]);
           }
         }
       }

@@ -167,14 +167,8 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
 #pragma unroll
         for (int u = 0; u < kFoldBatch; ++u)
           if (cix[u] >= 0) {
-            unsigned s = hslot(jj[u], kCapShift);
-            int kf = keys[s];
-#pragma unroll 1
-            for (int it = 1; kf != jj[u] && kf != EMPTY && it < kCap; ++it) {
-              s = (s + 1) & (kCap - 1);
-              kf = keys[s];
-            }
-            if (kf == jj[u]) unsafeAtomicAdd(g.F_out + cix[u], ww[u] * vals[s]);
+            const int s = hash_find64(keys, jj[u]);
+            if (s >= 0) unsafeAtomicAdd(g.F_out + cix[u], ww[u] * vals[s]);
           }
       }
     } else {
@@ -182,14 +176,8 @@ __global__ __launch_bounds__(kRmWaves * WAVE) void k_rowmul_short(RowMulArgs g,
       const int o = h.o0 + sub < h.o1 ? h.o0 + sub : -1;
       const int c = ld_i32(rOc, o);
       if (o >= 0) {
-        unsigned s = hslot(c, kCapShift);
-        int kf = keys[s];
-#pragma unroll 1
-        for (int it = 1; kf != c && kf != EMPTY && it < kCap; ++it) {
-          s = (s + 1) & (kCap - 1);
-          kf = keys[s];
-        }
-        g.O_val[o] = kf == c ? vals[s] : 0.0;
+        const int s = hash_find64(keys, c);
+        g.O_val[o] = s >= 0 ? vals[s] : 0.0;
       }
     }
     wave_sync();

@@ -128,4 +128,17 @@ __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, dou
 }
 
 
+// Slot of key in a row's 64-slot table, or -1 (the table's inserts are complete).  Rolled: the
+// first read settles nearly every lookup.
+__device__ __forceinline__ int hash_find64(const int* keys, int key) {
+  unsigned s = hslot(key, kCapShift);
+  int kf = keys[s];
+#pragma unroll 1
+  for (int it = 1; kf != key && kf != EMPTY && it < kCap; ++it) {
+    s = (s + 1) & (kCap - 1);
+    kf = keys[s];
+  }
+  return kf == key ? (int)s : -1;
+}
+
 }  // namespace ptapk
