@@ -166,6 +166,16 @@ def _fd(plan, g, which, k, rows_mask, h=1e-6):
     return diff
 
 
+def test_backward_full_64cubed_against_oracle(c5):
+    """Every entry of dA and dP at the differentiation workload's size against the oracle's
+    adjoint, under the FP64 criterion with the adjoint of |A|, |P|, |W| as the scale."""
+    g, plan, rp, col, W, dA, dP = c5
+    rA, rP = oracle.ptap_backward(g.A, g.P, rp, col, W)
+    bA, bP = _bounds(g.A, g.P, rp, col, W)
+    assert_close(dA, rA, bA, "dA")
+    assert_close(dP, rP, bP, "dP")
+
+
 def test_backward_finite_differences_64cubed(c5):
     g, plan, rp, col, W, dA, dP = c5
     A, P = g.A, g.P
