@@ -88,9 +88,14 @@ def test_c2_full_constant_coefficients_bit_exact():
 
 @pytest.mark.parametrize("name", ["c3a", "c3b"])
 def test_c3_full_smoothed_aggregation(name):
+    """Merged (owner fold), two-step (its short-row kernel walks the rows of P^T, up to 125
+    entries, 32 at a time) and the atomic fold, each against the same oracle C."""
     A, P, _ = gen.galerkin_workload(name)
     ref = oracle.ptap(A, P)
-    _check_full(GpuProblem(A, P), ref)
+    g = GpuProblem(A, P)
+    _check_full(g, ref)
+    _check_full(g, ref, algo="twostep")
+    _check_full(g, ref, algo="merged", fold="atomic")
 
 
 def test_c3c_block_sampled_rows():
