@@ -219,6 +219,8 @@ struct ptap_plan {
   int* tile_slot = nullptr;
   int* tile_fptr = nullptr;
   int* tile_fine = nullptr;
+  int* off_fptr = nullptr;  // two-pass all-at-once: per tile, rows with owned off-block entries
+  int* off_fine = nullptr;
   std::vector<int> host_fptr;
   std::vector<TileClass> tclasses;
   bool any_tile_global = false;
@@ -752,7 +754,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       int* tcnt = t.get<int>(T);
       int* trmax = t.get<int>(2 * (size_t)T);
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, false, tcnt, trmax, nullptr,
-                             nullptr, s));
+                             nullptr, PART_ALL, P->opt.nblocks, s));
       std::vector<int> hcnt = to_host(tcnt, T, s);
       std::vector<int> hrmax = to_host(trmax, 2 * (size_t)T, s);
       t.put(tcnt);
@@ -769,8 +771,31 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       to_device(P->tile_fptr, fptr, s);
       P->host_fptr = fptr;
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
-                             P->tile_fptr, P->tile_fine, s));
+                             P->tile_fptr, P->tile_fine, PART_ALL, P->opt.nblocks, s));
       P->rows_formed = acc;
+      // two-pass all-at-once (Alg. 8): the first pass walks only each tile's rows that own an
+      // off-block entry there
+      if (P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1) {
+        int* ocnt = t.get<int>(T);
+        int* ormax = t.get<int>(2 * (size_t)T);
+        hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, false, ocnt, ormax, nullptr,
+                               nullptr, PART_OFF, P->opt.nblocks, s));
+        std::vector<int> hoc = to_host(ocnt, T, s);
+        t.put(ocnt);
+        t.put(ormax);
+        std::vector<int> ofptr(T + 1, 0);
+        long long oacc = 0;
+        for (int k = 0; k < T; ++k) {
+          oacc += hoc[k];
+          ofptr[k + 1] = (int)oacc;  // at most acc, which fits
+        }
+        P->off_fptr = t.get<int>(T + 1);
+        P->off_fine = t.get<int>(oacc);
+        to_device(P->off_fptr, ofptr, s);
+        hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
+                               P->off_fptr, P->off_fine, PART_OFF, P->opt.nblocks, s));
+        P->rows_formed += oacc;
+      }
       // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
       // its (empty) rows are written
       std::map<std::tuple<int, int, int>, std::vector<int>> groups;
@@ -796,8 +821,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         to_device(tc.tiles, kv.second, s);
         tc.host_tiles = kv.second;
         // the short-row kernel pairs consecutive rows of a tile's list: order them by owned count
-        if (tc.fast)
+        if (tc.fast) {
           hipck(launch_tile_order(pat, tc.tiles, tc.count, P->tile_fptr, P->tile_fine, P->tile_slot, s));
+          if (P->off_fptr)
+            hipck(launch_tile_order(pat, tc.tiles, tc.count, P->off_fptr, P->off_fine, P->tile_slot, s));
+        }
         if (tc.tile_global) P->any_tile_global = true;
         if (tc.hash_global)
           spill_need_ints = std::max(spill_need_ints, (size_t)tc.count * kWavesPerBlock * tc.cap);
@@ -923,6 +951,8 @@ static NumericArgs numeric_args(ptap_plan* P, const double* A_val, const double*
   a.C_val = C_val;
   a.K = P->opt.nblocks;
   a.part = part;
+  a.off_fptr = P->off_fptr;
+  a.off_fine = P->off_fine;
   return a;
 }
 

@@ -74,10 +74,12 @@ hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row
                          const int* AP_rowptr, const int* AP_col, const RowClass& rc, bool fill,
                          int* cnt_out, const int* C_rowptr, int* C_col, int* gtab, hipStream_t s);
 // Count pass: cnt_out[t] = number of distinct fine rows of tile t; rmax_out[2t] = max |R_I| and
-// rmax_out[2t+1] = max row length of A and of P over them.  Fill pass: the sorted rows.
+// rmax_out[2t+1] = max row length of A and of P over them.  Fill pass: the sorted rows.  Only
+// entries P(I,i) that part (PART_ALL, PART_OFF, PART_ON with K blocks) takes make I a row of t.
 hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
                             const TileSet& ts, int ntiles, const int* r, bool fill, int* cnt_out,
-                            int* rmax_out, const int* fptr, int* fine, hipStream_t s);
+                            int* rmax_out, const int* fptr, int* fine, int part, int K,
+                            hipStream_t s);
 // Reorder the lists of the given tiles (in place) by the count of the row's entries of P the
 // tile owns.
 hipError_t launch_tile_order(const Patterns& p, const int* tiles, int ntiles, const int* fptr,
@@ -93,6 +95,10 @@ struct NumericArgs {
   double* C_val;
   int K;
   int part;  // FoldPart
+  // two-pass all-at-once: per tile, the fine rows with off-block entries owned by the tile (the
+  // first pass walks only these); null otherwise
+  const int* off_fptr;
+  const int* off_fine;
 };
 hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s);
 

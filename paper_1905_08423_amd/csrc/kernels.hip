@@ -425,17 +425,19 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
                                                           const int* __restrict__ P_rowptr,
                                                           int* cnt_out, int* rmax_out,
                                                           const int* __restrict__ fptr,
-                                                          int* fine) {
+                                                          int* fine, int part, int n, int m, int K) {
   __shared__ unsigned bits[kWindowBits / 32];
   __shared__ int red[kTileBlock / WAVE];
   const int tile = blockIdx.x;
   const int tp = ts.ptr[tile], nr = ts.ptr[tile + 1] - tp;
+  const int ts_n = n, ts_m = m;
   // candidates: the column lists of P for every row of the tile (one thread per tile row)
   int lo = INT32_MAX, hi = -1, rmax = 0, lmax = 0;
   for (int q = threadIdx.x; q < nr; q += kTileBlock) {
     const int i = ts.rows[tp + q];
     for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
       const int I = pt_row[t];
+      if (!part_takes(part, I, i, ts_n, ts_m, K)) continue;
       lo = min(lo, I);
       hi = max(hi, I);
       if (!FILL) {
@@ -457,6 +459,7 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_fine(const int* __restrict_
     for (int q = threadIdx.x; q < nr; q += kTileBlock) {
       const int i = ts.rows[tp + q];
       for (int t = pt_ptr[i]; t < pt_ptr[i + 1]; ++t) {
+        if (!part_takes(part, pt_row[t], i, ts_n, ts_m, K)) continue;
         const long long d = (long long)pt_row[t] - wb;
         if (d >= 0 && d < kWindowBits) atomicOr(bits + (d >> 5), 1u << (d & 31));
       }
@@ -558,14 +561,15 @@ hipError_t launch_tile_order(const Patterns& p, const int* tiles, int ntiles, co
 
 hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_row,
                             const TileSet& ts, int ntiles, const int* r, bool fill, int* cnt_out,
-                            int* rmax_out, const int* fptr, int* fine, hipStream_t s) {
+                            int* rmax_out, const int* fptr, int* fine, int part, int K,
+                            hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (fill)
     hipLaunchKernelGGL(k_tile_fine<true>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row, ts,
-                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
+                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine, part, p.n, p.m, K);
   else
     hipLaunchKernelGGL(k_tile_fine<false>, dim3(ntiles), dim3(kTileBlock), 0, s, pt_ptr, pt_row, ts,
-                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine);
+                       r, p.A_rowptr, p.P_rowptr, cnt_out, rmax_out, fptr, fine, part, p.n, p.m, K);
   return hipGetLastError();
 }
 
@@ -734,14 +738,18 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
   table_clear<HG>(keys, vals, cap);
   __syncthreads();
 
-  const int f1 = tile_fptr[tile + 1];
   // a.part < 0: the two passes of Alg. 8 (off-block entries, then on-block entries, R_I formed
-  // in each); otherwise one pass over the given part.
+  // in each; the first pass walks only the tile's rows with off-block entries); otherwise one
+  // pass over the given part.
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
-    for (int f = tile_fptr[tile] + wid; f < f1; f += kWavesPerBlock) {
-      const int I = tile_fine[f];
+    const bool off_list = pass == 0 && npass == 2 && a.off_fptr != nullptr;
+    const int* fine = off_list ? a.off_fine : tile_fine;
+    const int f0 = off_list ? a.off_fptr[tile] : tile_fptr[tile];
+    const int f1 = off_list ? a.off_fptr[tile + 1] : tile_fptr[tile + 1];
+    for (int f = f0 + wid; f < f1; f += kWavesPerBlock) {
+      const int I = fine[f];
       const int p0 = p.P_rowptr[I], p1 = p.P_rowptr[I + 1];
       bool any = false;
       for (int e = p0 + ln; e < p1; e += WAVE) {

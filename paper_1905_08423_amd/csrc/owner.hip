@@ -135,7 +135,6 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   vals[sub + kHalf] = 0.0;
   __syncthreads();
 
-  const int f0 = tile_fptr[tile], f1 = tile_fptr[tile + 1];
   const int step = 2 * NW;
   const int nnzP = p.P_rowptr[p.n];
   const __amdgpu_buffer_rsrc_t rA = buffer_rsrc(p.A_rowptr, (unsigned)(p.n + 1) * 4u);
@@ -149,6 +148,11 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
+    // the first of two passes walks only the tile's rows with off-block entries (Alg. 8, loop 1)
+    const bool off_list = pass == 0 && npass == 2 && a.off_fptr != nullptr;
+    const int* fine = off_list ? a.off_fine : tile_fine;
+    const int f0 = off_list ? a.off_fptr[tile] : tile_fptr[tile];
+    const int f1 = off_list ? a.off_fptr[tile + 1] : tile_fptr[tile + 1];
     // Software pipeline over the wavefront's row pairs f, f+step, f+2*step, ...: while the
     // pair being folded (cur) works in LDS, the next two pairs advance one load stage each
     // (entries of A and P -> extent of the row of P), so each dependent load overlaps one
@@ -156,7 +160,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
     // loaded once per 32 iterations.
     const int fb = f0 + 2 * wid + half;
     int it0 = 0;
-    Stage2 hb = hdr_load(tile_fine, fb + sub * step, f1, rA, rP);
+    Stage2 hb = hdr_load(fine, fb + sub * step, f1, rA, rP);
     Stage4 cur = st_pext<PEXT>(st_entries<PEXT>(hdr_get(hb, 0, half), g, sub), g);
     Stage3 nxt = st_entries<PEXT>(hdr_get(hb, 1, half), g, sub);
     for (int it = 0, f = f0 + 2 * wid; f < f1; ++it, f += step) {
@@ -203,7 +207,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
       if (k == kHalf) {
         it0 += kHalf;
         k = 0;
-        hb = hdr_load(tile_fine, fb + (it0 + sub) * step, f1, rA, rP);
+        hb = hdr_load(fine, fb + (it0 + sub) * step, f1, rA, rP);
       }
       const Stage2 h2 = hdr_get(hb, k, half);
       const Stage4 nxt4 = st_pext<PEXT>(nxt, g);
