@@ -104,26 +104,51 @@ inline int next_pow2(long long v) {
 // least 2*need slots (load factor <= 1/2), never below one slot per lane.
 inline int cap_for(long long need) { return std::max(64, next_pow2(2 * std::max(need, 1LL))); }
 
-// Group rows (given in ascending order with their key-count bounds) by table capacity.  Rows
-// with a bound of zero are dropped (they add nothing).  Capacities above `lds_max` go to
-// device-memory tables.
+// log2 of cap_for(need) for need >= 1: the smallest power of two >= 2*need, at least 64 and at
+// most 2^30.
+inline int cap_log2(long long need) {
+  const unsigned long long v = 2ULL * (unsigned long long)need;
+  const int b = v <= 64 ? 6 : 64 - __builtin_clzll(v - 1);
+  return std::min(b, 30);
+}
+
+// Group rows (given in ascending order with their key-count bounds) by table capacity, by a
+// stable counting sort over the capacity's exponent.  Rows with a bound of zero are dropped (they
+// add nothing).  Capacities above `lds_max` go to device-memory tables.
 std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
                                    const std::vector<long long>& need, int lds_max, hipStream_t s) {
-  std::map<int, std::vector<int>> by_cap;
+  constexpr int kBins = 31;
+  std::vector<unsigned char> bin(rows.size());
+  size_t cnt[kBins] = {};
   for (size_t k = 0; k < rows.size(); ++k) {
-    if (need[k] <= 0) continue;
-    by_cap[cap_for(need[k])].push_back(rows[k]);
+    if (need[k] <= 0) {
+      bin[k] = 0xFF;
+      continue;
+    }
+    bin[k] = (unsigned char)cap_log2(need[k]);
+    ++cnt[bin[k]];
+  }
+  size_t off[kBins + 1] = {};
+  for (int b = 0; b < kBins; ++b) off[b + 1] = off[b] + cnt[b];
+  std::vector<int> sorted(off[kBins]);
+  {
+    size_t pos[kBins];
+    std::copy(off, off + kBins, pos);
+    for (size_t k = 0; k < rows.size(); ++k)
+      if (bin[k] != 0xFF) sorted[pos[bin[k]]++] = rows[k];
   }
   std::vector<RowClass> out;
-  for (auto& kv : by_cap) {
+  for (int b = 0; b < kBins; ++b) {
+    if (!cnt[b]) continue;
     RowClass rc;
-    rc.cap = kv.first;
-    rc.global = kv.first > lds_max;
-    rc.count = (int)kv.second.size();
-    rc.rows = t.get<int>(kv.second.size());
-    to_device(rc.rows, kv.second, s);
+    rc.cap = 1 << b;
+    rc.global = rc.cap > lds_max;
+    rc.count = (int)cnt[b];
+    rc.rows = t.get<int>(cnt[b]);
+    hipck(hipMemcpyAsync(rc.rows, sorted.data() + off[b], cnt[b] * sizeof(int), hipMemcpyHostToDevice, s));
     out.push_back(rc);
   }
+  hipck(hipStreamSynchronize(s));  // `sorted` goes out of scope
   return out;
 }
 
@@ -446,15 +471,15 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   int* r = t.get<int>(n);
   hipck(launch_fill_i32(r, 0, n, s));
   {
-    long long* w = t.get<long long>(n);
-    hipck(launch_row_work(pat, w, s));
-    std::vector<long long> hw = to_host(w, n, s);
+    int* w = t.get<int>(n);
+    hipck(launch_row_work(pat, w, s));  // min(w_I, m)
+    std::vector<int> hw = to_host(w, n, s);
     t.put(w);
     std::vector<int> rows(n);
     std::vector<long long> need(n);
     for (int I = 0; I < n; ++I) {
       rows[I] = I;
-      need[I] = std::min<long long>(hw[I], m);
+      need[I] = hw[I];
     }
     std::vector<RowClass> cls = make_classes(t, rows, need, P->lds_keys_max, s);
     size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up

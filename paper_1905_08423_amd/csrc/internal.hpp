@@ -62,7 +62,7 @@ hipError_t launch_stream_sum(const double* x, long long n, double* out, hipStrea
 hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_t s);
 hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
                                  int* t_row, int* t_pos, hipStream_t s);
-hipError_t launch_row_work(const Patterns& p, long long* w, hipStream_t s);
+hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s);  // min(w_I, m)
 hipError_t launch_ap_row_count(const Patterns& p, const RowClass& rc, int* r_out, int* gtab,
                                hipStream_t s);
 hipError_t launch_ap_row_fill(const Patterns& p, const RowClass& rc, const int* AP_rowptr,

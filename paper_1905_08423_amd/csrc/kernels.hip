@@ -148,7 +148,9 @@ hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, i
 
 // w_I = sum over J in row I of A of nnz(P(J,:)): the number of products of row I of AP, an
 // upper bound on |R_I|.
-__global__ void k_row_work(Patterns p, long long* w) {
+// w[I] = min(sum_{J in A(I,:)} nnz(P(J,:)), m): the product count of row I of AP, which bounds
+// |R_I| (at most m distinct columns).
+__global__ void k_row_work(Patterns p, int* w) {
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= p.n) return;
   long long s = 0;
@@ -156,10 +158,10 @@ __global__ void k_row_work(Patterns p, long long* w) {
     const int J = p.A_col[k];
     s += p.P_rowptr[J + 1] - p.P_rowptr[J];
   }
-  w[I] = s;
+  w[I] = (int)(s < p.m ? s : p.m);
 }
 
-hipError_t launch_row_work(const Patterns& p, long long* w, hipStream_t s) {
+hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_work, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, w);
   return hipGetLastError();
