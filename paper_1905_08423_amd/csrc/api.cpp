@@ -6,8 +6,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <exception>
 #include <map>
 #include <new>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -160,19 +162,20 @@ size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
 }
 
 // Tiles of rows of C for the owner fold, grown breadth-first over the graph of C's pattern (row
-// r is adjacent to the columns of row r): starting from the lowest unassigned row, rows are taken
-// in BFS order while the tile holds at most TE entries and TR rows.  On meshes this gives compact
-// tiles, so fewer fine rows touch two tiles than with contiguous ranges of rows.  A row longer
-// than TE forms a tile of its own (tglob = 1: kept in device memory).  Rows within a tile are
-// listed in ascending order.
-void grow_tiles(int m, const std::vector<int>& cptr, const std::vector<int>& ccol, int TE, int TR,
+// r is adjacent to the columns of row r): starting from the lowest unassigned row of the range
+// [lo, hi), rows of that range are taken in BFS order while the tile holds at most TE entries and
+// TR rows.  On meshes this gives compact tiles, so fewer fine rows touch two tiles than with
+// contiguous ranges of rows.  A row longer than TE forms a tile of its own (tglob = 1: kept in
+// device memory).  Rows within a tile are listed in ascending order.  Only state[lo..hi) is read
+// or written, so ranges can be grown at the same time.
+void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE, int TR, int* state,
                 std::vector<int>& tptr, std::vector<int>& trows, std::vector<char>& tglob) {
-  std::vector<int> state(m, -1);  // -1 free, -2 queued for the tile being grown, >= 0 tile id
+  // state: -1 free, -2 queued for the tile being grown, >= 0 taken
   std::vector<int> queue;
   tptr.assign(1, 0);
   trows.clear();
   tglob.clear();
-  for (int seed = 0; seed < m; ++seed) {
+  for (int seed = lo; seed < hi; ++seed) {
     if (state[seed] != -1) continue;
     const int T = (int)tglob.size();
     if (cptr[seed + 1] - cptr[seed] > TE) {
@@ -200,7 +203,7 @@ void grow_tiles(int m, const std::vector<int>& cptr, const std::vector<int>& cco
       trows.push_back(r);
       for (int k = cptr[r]; k < cptr[r + 1]; ++k) {
         const int c = ccol[k];
-        if (c >= 0 && c < m && state[c] == -1) {
+        if (c >= lo && c < hi && state[c] == -1) {
           state[c] = -2;
           queue.push_back(c);
         }
@@ -210,6 +213,50 @@ void grow_tiles(int m, const std::vector<int>& cptr, const std::vector<int>& cco
     std::sort(trows.begin() + (long)start, trows.end());
     tptr.push_back((int)trows.size());
     tglob.push_back(0);
+  }
+}
+
+// All rows of C in tiles: the rows are split into up to kGrowParts contiguous ranges of at least
+// kGrowPartRows rows, grown on threads of their own, and the ranges' tiles listed in range order.
+// The split depends on m only, so the tiles are the same on every machine.
+constexpr int kGrowParts = 8;
+constexpr int kGrowPartRows = 32768;
+
+void grow_tiles(int m, const int* cptr, const int* ccol, int TE, int TR, std::vector<int>& tptr,
+                std::vector<int>& trows, std::vector<char>& tglob) {
+  const int parts = (int)std::max<long long>(1, std::min<long long>(kGrowParts, m / kGrowPartRows));
+  std::vector<int> state(m, -1);
+  std::vector<std::vector<int>> pp(parts), pr(parts);
+  std::vector<std::vector<char>> pg(parts);
+  std::vector<std::exception_ptr> err(parts);
+  auto work = [&](int p) {
+    try {
+      const int lo = (int)((long long)m * p / parts), hi = (int)((long long)m * (p + 1) / parts);
+      grow_range(lo, hi, cptr, ccol, TE, TR, state.data(), pp[p], pr[p], pg[p]);
+    } catch (...) {
+      err[p] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int p = 1; p < parts; ++p) {
+    try {
+      th.emplace_back(work, p);
+    } catch (...) {
+      work(p);  // no thread to spare: grow the range here
+    }
+  }
+  work(0);
+  for (std::thread& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  tptr.assign(1, 0);
+  trows.clear();
+  tglob.clear();
+  for (int p = 0; p < parts; ++p) {
+    const int base = (int)trows.size();
+    for (size_t k = 1; k < pp[p].size(); ++k) tptr.push_back(base + pp[p][k]);
+    trows.insert(trows.end(), pr[p].begin(), pr[p].end());
+    tglob.insert(tglob.end(), pg[p].begin(), pg[p].end());
   }
 }
 
@@ -762,7 +809,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
       std::vector<int> tptr, trows;
       std::vector<char> tglob;
-      grow_tiles(m, h_c_ptr, h_c_col, TE, TR, tptr, trows, tglob);
+      grow_tiles(m, h_c_ptr.data(), h_c_col.data(), TE, TR, tptr, trows, tglob);
       const int T = (int)tglob.size();
       if (T >= (1 << (31 - kTileRowBits))) fail(PTAP_ERR_TOO_LARGE);
       std::vector<int> slot(m, -1);
