@@ -165,7 +165,9 @@ ptap_status ptap_plan_create_bsr(ptap_plan** out, int32_t nb, int32_t mb, int32_
 /*
  * Symbolic phase (Section 2; Alg. 7/9 for all-at-once and merged, Alg. 5 for two-step):
  * computes and keeps the pattern of C and every index structure the numeric phase needs.
- * Synchronises the stream (it reads nnz(C) and the row classes on the host).
+ * Synchronises the stream (it reads nnz(C) and the row classes on the host).  For the owner
+ * fold it groups C's rows into tiles on the host with up to 8 threads of its own (joined before
+ * it returns); the tiles depend on the patterns only, not on the machine.
  * Errors: PTAP_ERR_STATE if already done, PTAP_ERR_TOO_LARGE, PTAP_ERR_OOM, PTAP_ERR_HIP.
  */
 ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream);
