@@ -42,10 +42,12 @@ typedef enum ptap_status {
   PTAP_OK = 0,
   PTAP_ERR_INPUT = 1,       /* malformed CSR, shape mismatch, bad option, NULL argument */
   PTAP_ERR_TOO_LARGE = 2,   /* a count would overflow int32 indexing */
-  PTAP_ERR_OOM = 3,         /* the allocator returned NULL; the plan is left unchanged */
+  PTAP_ERR_OOM = 3,         /* the allocator returned NULL or host memory ran out; the plan is
+                               left unchanged */
   PTAP_ERR_HIP = 4,         /* a HIP runtime call failed; see ptap_last_hip_error */
   PTAP_ERR_STATE = 5,       /* call out of order (e.g. numeric before symbolic) */
-  PTAP_ERR_UNSUPPORTED = 6  /* option combination not provided */
+  PTAP_ERR_UNSUPPORTED = 6  /* option combination not provided (also any other host library
+                               error, which is never let through the interface) */
 } ptap_status;
 
 /* Algorithm choice (the paper's "allatonce", "merged" and "two-step", Section 4). */

@@ -36,6 +36,22 @@ inline void hipck(hipError_t e) {
 
 inline void fail(ptap_status s) { throw Failure{s}; }
 
+// The status for the exception being handled, called inside a catch (...) block: a Failure's own,
+// PTAP_ERR_OOM when host memory ran out, and PTAP_ERR_UNSUPPORTED for anything else from the
+// standard library (a thread that could not start, a size beyond a container's limit), so that no
+// exception crosses the C interface.
+ptap_status caught_status() {
+  try {
+    throw;
+  } catch (const Failure& f) {
+    return f.status;
+  } catch (const std::bad_alloc&) {
+    return PTAP_ERR_OOM;
+  } catch (...) {
+    return PTAP_ERR_UNSUPPORTED;
+  }
+}
+
 void* default_alloc(size_t bytes, void*) {
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -381,7 +397,7 @@ const char* ptap_status_string(ptap_status s) {
     case PTAP_OK: return "ok";
     case PTAP_ERR_INPUT: return "invalid input";
     case PTAP_ERR_TOO_LARGE: return "count overflows int32 indexing";
-    case PTAP_ERR_OOM: return "device allocation failed";
+    case PTAP_ERR_OOM: return "out of memory (device allocator or host)";
     case PTAP_ERR_HIP: return "HIP runtime error";
     case PTAP_ERR_STATE: return "call out of order";
     case PTAP_ERR_UNSUPPORTED: return "unsupported option combination";
@@ -395,8 +411,9 @@ ptap_status ptap_stream_sum(const double* x, int64_t n, double* out, hipStream_t
   if (n < 0 || !out || (n > 0 && !x) || ((uintptr_t)x & 15u)) return PTAP_ERR_INPUT;
   try {
     hipck(launch_stream_sum(x, n, out, s));
-  } catch (const Failure& f) {
-    return f.status;
+  } catch (...) {
+    const ptap_status st = caught_status();
+    return st;
   }
   return PTAP_OK;
 }
@@ -442,10 +459,11 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
       p->lds_keys_max = std::min(p->lds_keys_max, (int)o.hash_slots);
     }
     if (o.validate) validate_patterns(p, stream);
-  } catch (const Failure& f) {
+  } catch (...) {
+    const ptap_status st = caught_status();
     p->mem.release_all();
     delete p;
-    return f.status;
+    return st;
   }
   *out = p;
   return PTAP_OK;
@@ -975,7 +993,8 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
   // Run on a scratch copy of the plan's state so that a failure leaves the plan unchanged.
   try {
     symbolic_impl(plan, stream);
-  } catch (const Failure& f) {
+  } catch (...) {
+    const ptap_status st = caught_status();
     // wait for the launches already queued, then release everything the failed phase allocated
     (void)hipStreamSynchronize(stream);
     (void)hipGetLastError();
@@ -995,7 +1014,7 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
     fresh.lds_keys_max = plan->lds_keys_max;
     plan->~ptap_plan();
     new (plan) ptap_plan(std::move(fresh));
-    return f.status;
+    return st;
   }
   plan->sym_done = true;
   return PTAP_OK;
@@ -1091,8 +1110,9 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
         hipck(launch_owner_numeric(a, c, ts, P->tile_fptr, P->tile_fine, P->TE,
                                    P->opt.xcd_remap != 0, P->gtab, P->gval, s));
     }
-  } catch (const Failure& f) {
-    return f.status;
+  } catch (...) {
+    const ptap_status st = caught_status();
+    return st;
   }
   return PTAP_OK;
 }
@@ -1112,8 +1132,9 @@ ptap_status ptap_backward(ptap_plan* P, const double* A_val, const double* P_val
     for (auto& c : P->bwd_rows)
       hipck(c.fast ? launch_backward_short(a, dC_val, dA_val, dP_val, c, s)
                    : launch_backward(a, dC_val, dA_val, dP_val, c, P->gtab, P->gval, s));
-  } catch (const Failure& f) {
-    return f.status;
+  } catch (...) {
+    const ptap_status st = caught_status();
+    return st;
   }
   return PTAP_OK;
 }
@@ -1202,11 +1223,12 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
     hipck(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     b->grid = std::max(1, cus * 2);
     hipck(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-  } catch (const Failure& f) {
+  } catch (...) {
+    const ptap_status st = caught_status();
     if (b->cap) (void)hipStreamDestroy(b->cap);
     b->mem.release_all();
     delete b;
-    return f.status;
+    return st;
   }
   *out = b;
   return PTAP_OK;
@@ -1279,8 +1301,9 @@ ptap_status ptap_batch_numeric(ptap_batch* b, const double* const* A_vals,
           return PTAP_ERR_INPUT;
     }
     hipck(hipGraphLaunch(b->exec, stream));
-  } catch (const Failure& f) {
-    return f.status;
+  } catch (...) {
+    const ptap_status st = caught_status();
+    return st;
   }
   return PTAP_OK;
 }
