@@ -130,20 +130,22 @@ inline int cap_log2(long long need) {
   return std::min(b, 30);
 }
 
-// Group rows (given in ascending order with their key-count bounds) by table capacity, by a
-// stable counting sort over the capacity's exponent.  Rows with a bound of zero are dropped (they
-// add nothing).  Capacities above `lds_max` go to device-memory tables.
-std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
-                                   const std::vector<long long>& need, int lds_max, hipStream_t s) {
+// Group rows by table capacity, by a stable counting sort over the capacity's exponent: row(k)
+// with the key-count bound need(k), k = 0 .. count-1, rows in ascending order.  Rows with a bound
+// of zero are dropped (they add nothing).  Capacities above `lds_max` go to device-memory tables.
+template <class Row, class Need>
+std::vector<RowClass> make_classes_by(Tracker& t, size_t count, Row row, Need need, int lds_max,
+                                      hipStream_t s) {
   constexpr int kBins = 31;
-  std::vector<unsigned char> bin(rows.size());
+  std::vector<unsigned char> bin(count);
   size_t cnt[kBins] = {};
-  for (size_t k = 0; k < rows.size(); ++k) {
-    if (need[k] <= 0) {
+  for (size_t k = 0; k < count; ++k) {
+    const long long v = need(k);
+    if (v <= 0) {
       bin[k] = 0xFF;
       continue;
     }
-    bin[k] = (unsigned char)cap_log2(need[k]);
+    bin[k] = (unsigned char)cap_log2(v);
     ++cnt[bin[k]];
   }
   size_t off[kBins + 1] = {};
@@ -152,8 +154,8 @@ std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
   {
     size_t pos[kBins];
     std::copy(off, off + kBins, pos);
-    for (size_t k = 0; k < rows.size(); ++k)
-      if (bin[k] != 0xFF) sorted[pos[bin[k]]++] = rows[k];
+    for (size_t k = 0; k < count; ++k)
+      if (bin[k] != 0xFF) sorted[pos[bin[k]]++] = row(k);
   }
   std::vector<RowClass> out;
   for (int b = 0; b < kBins; ++b) {
@@ -168,6 +170,21 @@ std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
   }
   hipck(hipStreamSynchronize(s));  // `sorted` goes out of scope
   return out;
+}
+
+// The listed rows, with their bounds.
+std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
+                                   const std::vector<long long>& need, int lds_max, hipStream_t s) {
+  return make_classes_by(
+      t, rows.size(), [&](size_t k) { return rows[k]; }, [&](size_t k) { return need[k]; }, lds_max, s);
+}
+
+// Every row 0 .. need.size()-1, with the bound need[k].
+template <class T>
+std::vector<RowClass> make_classes_all(Tracker& t, const std::vector<T>& need, int lds_max, hipStream_t s) {
+  return make_classes_by(
+      t, need.size(), [](size_t k) { return (int)k; }, [&](size_t k) { return (long long)need[k]; },
+      lds_max, s);
 }
 
 size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
@@ -540,13 +557,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     hipck(launch_row_work(pat, w, s));  // min(w_I, m)
     std::vector<int> hw = to_host(w, n, s);
     t.put(w);
-    std::vector<int> rows(n);
-    std::vector<long long> need(n);
-    for (int I = 0; I < n; ++I) {
-      rows[I] = I;
-      need[I] = hw[I];
-    }
-    std::vector<RowClass> cls = make_classes(t, rows, need, P->lds_keys_max, s);
+    std::vector<RowClass> cls = make_classes_all(t, hw, P->lds_keys_max, s);
     size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
     int* gtab = gi ? t.get<int>(gi) : nullptr;
     for (auto& c : cls) hipck(launch_ap_row_count(pat, c, r, gtab, s));
@@ -569,13 +580,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->AP_rowptr = t.get<int>(n + 1);
     P->AP_col = t.get<int>(acc);
     to_device(P->AP_rowptr, h_ap_ptr, s);
-    std::vector<int> rows(n);
-    std::vector<long long> need(n);
-    for (int I = 0; I < n; ++I) {
-      rows[I] = I;
-      need[I] = hr[I];
-    }
-    P->ap_rows = make_classes(t, rows, need, P->lds_keys_max, s);
+    P->ap_rows = make_classes_all(t, hr, P->lds_keys_max, s);
     size_t gi = spill_ints(P->ap_rows, 2);
     int* gtab = gi ? t.get<int>(gi) : nullptr;
     for (auto& c : P->ap_rows) hipck(launch_ap_row_fill(pat, c, P->AP_rowptr, P->AP_col, gtab, s));
@@ -589,9 +594,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     hipck(launch_c_bound(P->pt_ptr, P->pt_row, r, m, bound, s));
     std::vector<long long> hb = to_host(bound, m, s);
     t.put(bound);
-    std::vector<int> rows(m);
-    for (int i = 0; i < m; ++i) rows[i] = i;
-    std::vector<RowClass> cls = make_classes(t, rows, hb, P->lds_keys_max, s);
+    std::vector<RowClass> cls = make_classes_all(t, hb, P->lds_keys_max, s);
     size_t gi = spill_ints(cls, 2);
     int* gtab = gi ? t.get<int>(gi) : nullptr;
     int* cnt = t.get<int>(m);
@@ -613,9 +616,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->C_rowptr = t.get<int>(m + 1);
     P->C_col = t.get<int>(acc);
     to_device(P->C_rowptr, h_c_ptr, s);
-    std::vector<long long> exact(m);
-    for (int i = 0; i < m; ++i) exact[i] = hc[i];
-    cls = make_classes(t, rows, exact, P->lds_keys_max, s);
+    cls = make_classes_all(t, hc, P->lds_keys_max, s);
     gi = spill_ints(cls, 2);
     gtab = gi ? t.get<int>(gi) : nullptr;
     for (auto& c : cls)
