@@ -547,7 +547,13 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     hipck(launch_transpose_fill(pat.P_rowptr, pat.P_col, n, cnt, P->pt_row, P->pt_pos, s));
     t.put(cnt);
   }
-  std::vector<int> hP_rowptr = to_host(pat.P_rowptr, (size_t)n + 1, s);
+  // Host copies of P's row pointers and of |R_I| (8 MB each at 128^3), made only by the branches
+  // that walk them row by row.
+  std::vector<int> hP_store, hr_store;
+  auto host_P_rowptr = [&]() -> const std::vector<int>& {
+    if (hP_store.size() != (size_t)n + 1) hP_store = to_host(pat.P_rowptr, (size_t)n + 1, s);
+    return hP_store;
+  };
 
   // --- |R_I| for every fine row (Alg. 1 / 2), tables sized by the product count w_I.
   int* r = t.get<int>(n);
@@ -564,11 +570,30 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     for (auto& c : cls) t.put(c.rows);
     t.put(gtab);
   }
-  std::vector<int> hr = to_host(r, n, s);
+  auto host_r = [&]() -> const std::vector<int>& {
+    if (hr_store.size() != (size_t)n) hr_store = to_host(r, n, s);
+    return hr_store;
+  };
+
+  // --- Counters for the statistics (rows needed, fold terms sum_I nnz(P(I,:)) |R_I|) and the
+  // longest rows, reduced on the device.
+  int rmax_all = 0, pmax_all = 0;
+  {
+    unsigned long long* st = t.get<unsigned long long>(4);
+    hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 8, s));
+    hipck(launch_row_stats(pat, r, st, s));
+    const std::vector<unsigned long long> h = to_host(st, 4, s);
+    t.put(st);
+    P->rows_needed = (long long)h[0];
+    P->fold_terms = (long long)h[1];
+    rmax_all = (int)h[2];
+    pmax_all = (int)h[3];
+  }
 
   // --- Two-step: the stored pattern of AP (rows sorted).
   std::vector<int> h_ap_ptr;
   if (two) {
+    const std::vector<int>& hr = host_r();
     h_ap_ptr.assign(n + 1, 0);
     long long acc = 0;
     for (int I = 0; I < n; ++I) {
@@ -627,18 +652,6 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->pattern_bytes = (int64_t)(m + 1 + acc) * (int64_t)sizeof(int);
   }
 
-  // --- Counters for the statistics: rows needed and fold terms sum_I nnz(P(I,:)) |R_I|.
-  long long needed = 0, terms = 0;
-  for (int I = 0; I < n; ++I) {
-    const int lp = hP_rowptr[I + 1] - hP_rowptr[I];
-    if (lp > 0 && hr[I] > 0) {
-      ++needed;
-      terms += (long long)lp * hr[I];
-    }
-  }
-  P->rows_needed = needed;
-  P->fold_terms = terms;
-
   size_t spill_need_ints = 0, spill_need_vals = 0;
   const int lmax = P->lds_hash_max;
 
@@ -681,6 +694,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     // limit).  Rows with at most 32 entries in AP(I,:) (in C(i,:) for the second product) take
     // the short-row kernel when every array fits its byte range.
     for (auto& c : P->ap_rows) t.put(c.rows);
+    const std::vector<int>& hr = host_r();
     std::vector<int> hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
     RowMulArgs g1{}, g2{};
     g1.nX = g1.nY = g2.nY = n;  // A and P have n rows, P^T has m
@@ -745,6 +759,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       gf.nF = m;
       gf.nnzF = P->nnzC;
       const bool short_ok = !twopass && rowmul_short_fits(gf);
+      const std::vector<int>& hr = host_r();
+      const std::vector<int>& hP_rowptr = host_P_rowptr();
       std::vector<int> hA_rowptr, hPc;
       if (short_ok) {
         hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
@@ -783,15 +799,6 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
-      int rmax_all = 0, pmax_all = 0;
-      {
-        std::vector<int> hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
-        for (int I = 0; I < n; ++I) {
-          rmax_all = std::max(rmax_all, hr[I]);
-          pmax_all = std::max(pmax_all, std::max(hP_rowptr[I + 1] - hP_rowptr[I],
-                                                 hA_rowptr[I + 1] - hA_rowptr[I]));
-        }
-      }
       // the short-row kernel addresses P's arrays and the row pointers with 32-bit byte offsets
       const bool fast_fits = P->nnzP * 8 < (1LL << 31) && P->nnzA * 8 < (1LL << 31) &&
                              ((long long)n + 1) * 4 < (1LL << 31);
@@ -941,6 +948,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // (R_I's columns are among them); they are counted exactly on the host.  Rows whose rows of C
   // under P(I,:) hold at most kAdjMaxWalk entries in total go to the short-row kernel.
   if (P->opt.backward) {
+    const std::vector<int>& hr = host_r();
+    const std::vector<int>& hP_rowptr = host_P_rowptr();
     std::vector<int> hPcol = to_host(pat.P_col, (size_t)P->nnzP, s);
     std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
     const int lds_max = lmax / 2 >= 64 ? lmax / 2 : 64;

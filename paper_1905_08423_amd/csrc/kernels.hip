@@ -10,7 +10,10 @@ namespace {
 
 constexpr int kThreads = kWavesPerBlock * WAVE;
 
-inline int grid_for(long long count, int threads, int cap_blocks = 65536) {
+// Blocks for `count` items at `threads` per block, at most cap_blocks.  The default cap covers any
+// int32 count with one thread per item at 256 threads per block (kernels without a grid-stride loop
+// rely on it); launches over a grid-stride loop pass a smaller cap.
+inline int grid_for(long long count, int threads, int cap_blocks = 1 << 23) {
   long long g = (count + threads - 1) / threads;
   if (g < 1) g = 1;
   if (g > cap_blocks) g = cap_blocks;
@@ -164,6 +167,52 @@ __global__ void k_row_work(Patterns p, int* w) {
 hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_work, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, w);
+  return hipGetLastError();
+}
+
+// Fine-row statistics of a plan, reduced over all rows: out[0] counts the rows with P(I,:) and R_I
+// both non-empty (the rows the fold needs), out[1] = sum_I nnz(P(I,:)) |R_I| (fold terms),
+// out[2] = max_I |R_I|, out[3] = max_I max(nnz(P(I,:)), nnz(A(I,:))).  out holds zeros on entry.
+// Launched with 256 threads per block.
+__global__ void k_row_stats(Patterns p, const int* __restrict__ r, unsigned long long* out) {
+  __shared__ unsigned long long sh[4][256];
+  const int t = threadIdx.x;
+  const int I = blockIdx.x * blockDim.x + t;
+  unsigned long long v[4] = {0, 0, 0, 0};
+  if (I < p.n) {
+    const int lp = p.P_rowptr[I + 1] - p.P_rowptr[I];
+    const int la = p.A_rowptr[I + 1] - p.A_rowptr[I];
+    const int rI = r[I];
+    if (lp > 0 && rI > 0) {
+      v[0] = 1;
+      v[1] = (unsigned long long)lp * (unsigned long long)rI;
+    }
+    v[2] = rI > 0 ? (unsigned long long)rI : 0;
+    const int l = lp > la ? lp : la;
+    v[3] = l > 0 ? (unsigned long long)l : 0;
+  }
+  for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      sh[0][t] += sh[0][t + h];
+      sh[1][t] += sh[1][t + h];
+      sh[2][t] = sh[2][t] > sh[2][t + h] ? sh[2][t] : sh[2][t + h];
+      sh[3][t] = sh[3][t] > sh[3][t + h] ? sh[3][t] : sh[3][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    atomicAdd(out, sh[0][0]);
+    atomicAdd(out + 1, sh[1][0]);
+    atomicMax(out + 2, sh[2][0]);
+    atomicMax(out + 3, sh[3][0]);
+  }
+}
+
+hipError_t launch_row_stats(const Patterns& p, const int* r, unsigned long long* out, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_stats, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, r, out);
   return hipGetLastError();
 }
 

@@ -101,6 +101,22 @@ def test_owner_tiles_over_uneven_row_ranges(side, ranges):
     _check_full(g, ref, algo="allatonce", fold="owner", nblocks=8)
 
 
+def test_rows_beyond_one_thread_per_row_grid_cap():
+    """17,000,000 fine and coarse rows: a 1D three-point operator and one smoothed-aggregation
+    step over single-node aggregates, so P is tridiagonal and n x n.  The symbolic kernels that
+    give one thread to each row (pattern validation, P's column lists, the row work w_I, the
+    bounds of C's rows) have to reach rows past 65,536 blocks of 256 threads (16,777,216 rows),
+    in A, in P and in C."""
+    n = 17_000_000
+    A = gen.laplacian7(n, 1, 1)
+    P = gen.smoothed_aggregation(A, n, 1, 1, agg=1, steps=1)
+    assert A.n_rows > 65536 * 256 and P.n_cols > 65536 * 256
+    ref = oracle.ptap(A, P)
+    g = GpuProblem(A, P)
+    st = _check_full(g, ref)
+    assert st["nnz_C"] == len(ref.col)
+
+
 @pytest.mark.parametrize("name", ["c3a", "c3b"])
 def test_c3_full_smoothed_aggregation(name):
     """Merged (owner fold), two-step (its short-row kernel walks the rows of P^T, up to 125
