@@ -257,14 +257,15 @@ __device__ __forceinline__ void tile_store(const int* __restrict__ rows, int tp,
 }
 
 // Contiguous K-way split of [0, total) as in the 1D block-row partition (Section 2): block b
-// owns [floor(b*total/K), floor((b+1)*total/K)).
-__device__ __forceinline__ int block_start(int b, int total, int K) {
-  return (int)(((long long)b * total) / K);
-}
+// owns [floor(b*total/K), floor((b+1)*total/K)).  The block of idx is the largest b with
+// floor(b*total/K) <= idx, that is b*total <= (idx+1)*K - 1, so b = floor(((idx+1)*K - 1) / total).
+// The FP64 quotient is within one of it and two 64-bit products settle it: 64-bit integer division
+// is a long instruction sequence on the GPU, and this runs for every row of the two-pass forms.
 __device__ __forceinline__ int block_of(int idx, int total, int K) {
-  int b = (int)(((long long)idx * K) / total);
-  while (b + 1 < K && block_start(b + 1, total, K) <= idx) ++b;
-  while (b > 0 && block_start(b, total, K) > idx) --b;
+  const long long num = (long long)(idx + 1) * K - 1;
+  int b = (int)((double)num / (double)total);
+  while ((long long)(b + 1) * total <= num) ++b;
+  while (b > 0 && (long long)b * total > num) --b;
   return b;
 }
 
