@@ -329,6 +329,7 @@ struct ptap_plan {
   std::vector<int> host_fptr;
   std::vector<TileClass> tclasses;
   bool any_tile_global = false;
+  bool wide_a = false;  // A's values pass 2 GiB: the short-row owner kernel reads them by address
 
   // atomic fold: general row classes and the short-row lists ([0] at most 32 entries in A(I,:),
   // [1] more)
@@ -799,9 +800,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
-      // the short-row kernel addresses P's arrays and the row pointers with 32-bit byte offsets
-      const bool fast_fits = P->nnzP * 8 < (1LL << 31) && P->nnzA * 8 < (1LL << 31) &&
+      // the short-row kernel addresses P's arrays, A's columns and the row pointers with 32-bit
+      // byte offsets, and A's values so too while they stay under 2 GiB (by address beyond)
+      const bool fast_fits = P->nnzP * 8 < (1LL << 31) && P->nnzA * 4 < (1LL << 31) &&
                              ((long long)n + 1) * 4 < (1LL << 31);
+      P->wide_a = P->nnzA * 8 >= (1LL << 31);
       const bool fast_all = fast_fits && rmax_all <= kFastMaxKeys && pmax_all <= kFastMaxKeys;
       const int nw = P->opt.owner_waves ? P->opt.owner_waves : kFastWaves;
       if (nw != 4 && nw != 8 && nw != 16) fail(PTAP_ERR_INPUT);
@@ -1054,6 +1057,7 @@ static NumericArgs numeric_args(ptap_plan* P, const double* A_val, const double*
   a.part = part;
   a.off_fptr = P->off_fptr;
   a.off_fine = P->off_fine;
+  a.wide_a = P->wide_a ? 1 : 0;
   return a;
 }
 
@@ -1209,6 +1213,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
       std::vector<std::pair<int, int2>> w;
       for (int k : b->level_plans[l]) {
         const ptap_plan* P = plans[k];
+        if (P->wide_a) continue;  // launched on its own (the batched kernel reads A by offset)
         for (const TileClass& c : P->tclasses) {
           if (!c.fast) continue;
           for (int tl : c.host_tiles)
@@ -1265,7 +1270,7 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       ptap_plan* P = b->plans[k];
       const NumericArgs& a = desc[k].a;
       if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
-      const bool single = b->level_plans[l].size() == 1;
+      const bool single = b->level_plans[l].size() == 1 || P->wide_a;
       for (const TileClass& c : P->tclasses) {
         if (err != hipSuccess) break;
         const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};

@@ -101,6 +101,9 @@ struct NumericArgs {
   // first pass walks only these); null otherwise
   const int* off_fptr;
   const int* off_fine;
+  // A's values span 2 GiB or more (nnz(A) >= 2^28): the short-row owner kernel reads them by
+  // 64-bit address instead of a 32-bit buffer offset
+  int wide_a;
 };
 hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s);
 

@@ -695,7 +695,8 @@ __global__ void k_pext(Patterns p, long long nnzA, int* __restrict__ out) {
        t += (long long)gridDim.x * blockDim.x) {
     const int J = p.A_col[t];
     const int ps = p.P_rowptr[J], len = p.P_rowptr[J + 1] - ps;
-    out[t] = (ps << 6) | (len < 63 ? len : 63);
+    // unsigned: starts up to 2^26 fill all 32 bits (the sign bit included)
+    out[t] = (int)(((unsigned)ps << 6) | (unsigned)(len < 63 ? len : 63));
   }
 }
 

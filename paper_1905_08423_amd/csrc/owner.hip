@@ -79,7 +79,15 @@ __device__ __forceinline__ Stage2 hdr_get(const Stage2& b, int k, int half) {
 // that may have issued a load has to assume it did, and vector loads complete in order).
 struct Gather {
   __amdgpu_buffer_rsrc_t A_rowptr, P_rowptr, A_col, P_col, P_val, A_val, slot, pext;
+  const double* A_val_ptr;  // the same values by address (read so where they pass 2 GiB)
 };
+
+// A value by 64-bit address, for arrays past the 2 GiB that a buffer offset reaches.  An invalid
+// entry (idx < 0) reads entry 0 and returns 0, so the load is still issued unconditionally.
+__device__ __forceinline__ double ld_dbl_wide(const double* __restrict__ p, int idx) {
+  const double v = p[idx < 0 ? 0 : idx];
+  return idx < 0 ? 0.0 : v;
+}
 
 template <bool PEXT>
 __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Gather& g, int sub) {
@@ -90,18 +98,19 @@ __device__ __forceinline__ Stage3 st_entries(const Stage2& q, const Gather& g, i
   r.pi = ld_i32(g.P_col, r.e);
   return r;
 }
-template <bool PEXT>
+template <bool PEXT, bool WIDE>
 __device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Gather& g) {
   Stage4 r{q.I, 0, 0, q.t, q.pi, q.e, -1, 0.0, 0.0};
   if (PEXT) {
-    r.ps = q.J >> 6;  // 0 for no entry (the load returned 0)
+    r.ps = (int)((unsigned)q.J >> 6);  // 0 for no entry (the load returned 0); unsigned: the
+                                        // start may use the sign bit
     r.pe = r.ps + (q.J & 63);
   } else {
     const v2u pr = ld_pair(g.P_rowptr, q.t >= 0 ? q.J : -1);
     r.ps = (int)pr[0];
     r.pe = (int)pr[1];
   }
-  r.av = ld_dbl(g.A_val, q.t);
+  r.av = WIDE ? ld_dbl_wide(g.A_val_ptr, q.t) : ld_dbl(g.A_val, q.t);
   const int sl = ld_i32(g.slot, q.e >= 0 ? q.pi : -1);
   r.sl = q.e >= 0 ? sl : -1;
   r.pw = ld_dbl(g.P_val, q.e);
@@ -110,7 +119,7 @@ __device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Gather& g) {
 
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
 // per-wavefront hash tables.  Ends with the tile written to C and a workgroup barrier.
-template <int NW, bool PEXT>
+template <int NW, bool PEXT, bool WIDE>
 __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, const TileSet& ts,
                                                 const int* __restrict__ tile_fptr,
                                                 const int* __restrict__ tile_fine, int TE,
@@ -142,9 +151,10 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   const __amdgpu_buffer_rsrc_t rPc = buffer_rsrc(p.P_col, (unsigned)nnzP * 4u);
   const __amdgpu_buffer_rsrc_t rPv = buffer_rsrc(a.P_val, (unsigned)nnzP * 8u);
   const unsigned nnzA = (unsigned)p.A_rowptr[p.n];
-  const __amdgpu_buffer_rsrc_t rAv = buffer_rsrc(a.A_val, nnzA * 8u);
+  const __amdgpu_buffer_rsrc_t rAv = buffer_rsrc(a.A_val, WIDE ? 0u : nnzA * 8u);
   const Gather g{rA, rP, buffer_rsrc(p.A_col, nnzA * 4u), rPc, rPv, rAv,
-                 buffer_rsrc(ts.slot, (unsigned)p.m * 4u), buffer_rsrc(a.A_pext, PEXT ? nnzA * 4u : 0u)};
+                 buffer_rsrc(ts.slot, (unsigned)p.m * 4u), buffer_rsrc(a.A_pext, PEXT ? nnzA * 4u : 0u),
+                 a.A_val};
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
@@ -161,7 +171,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
     const int fb = f0 + 2 * wid + half;
     int it0 = 0;
     Stage2 hb = hdr_load(fine, fb + sub * step, f1, rA, rP);
-    Stage4 cur = st_pext<PEXT>(st_entries<PEXT>(hdr_get(hb, 0, half), g, sub), g);
+    Stage4 cur = st_pext<PEXT, WIDE>(st_entries<PEXT>(hdr_get(hb, 0, half), g, sub), g);
     Stage3 nxt = st_entries<PEXT>(hdr_get(hb, 1, half), g, sub);
     for (int it = 0, f = f0 + 2 * wid; f < f1; ++it, f += step) {
       // (1) owned entries of P(I,:) of cur: the ones whose column is a row of this tile
@@ -210,7 +220,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
         hb = hdr_load(fine, fb + (it0 + sub) * step, f1, rA, rP);
       }
       const Stage2 h2 = hdr_get(hb, k, half);
-      const Stage4 nxt4 = st_pext<PEXT>(nxt, g);
+      const Stage4 nxt4 = st_pext<PEXT, WIDE>(nxt, g);
       const Stage3 nn3 = st_entries<PEXT>(h2, g, sub);
       // (4) fold the owned part of P(I,:) (x) R_I into the tile, one owned entry per half at a
       // time.  The owned entries leave (row start, row end, weight) in the half's records (free
@@ -253,7 +263,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   __syncthreads();
 }
 
-template <int NW, bool PEXT>
+template <int NW, bool PEXT, bool WIDE>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
                                                              TileSet ts,
                                                              const int* __restrict__ tile_fptr,
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
     const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
     b = x * q + min(x, rem) + k;
   }
-  owner_fast_tile<NW, PEXT>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
+  owner_fast_tile<NW, PEXT, WIDE>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
 }
 
 // Batched form: a persistent grid works through a list of (plan, tile) items, every item one tile
@@ -298,7 +308,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBa
       const int pk = __builtin_amdgcn_readfirstlane(w.x);
       const int tl = __builtin_amdgcn_readfirstlane(w.y);
       const OwnerBatchPlan& pl = plans[pk];
-      owner_fast_tile<NW, false>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
+      owner_fast_tile<NW, false, false>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
     }
   }
 }
@@ -307,18 +317,18 @@ size_t owner_fast_lds_bytes(int TE, int nw) {
   return (((size_t)TE * 12 + ((size_t)kTileRows + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
 }
 
-template <bool PEXT>
+template <bool PEXT, bool WIDE>
 static void launch_fast_nw(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
                            const int* tile_fptr, const int* tile_fine, int TE, int nw, int remap,
                            size_t lds, hipStream_t s) {
   if (nw == 16)
-    hipLaunchKernelGGL((k_owner_fast<16, PEXT>), dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
+    hipLaunchKernelGGL((k_owner_fast<16, PEXT, WIDE>), dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
                        ts, tile_fptr, tile_fine, TE, remap);
   else if (nw == 8)
-    hipLaunchKernelGGL((k_owner_fast<8, PEXT>), dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
+    hipLaunchKernelGGL((k_owner_fast<8, PEXT, WIDE>), dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
                        ts, tile_fptr, tile_fine, TE, remap);
   else
-    hipLaunchKernelGGL((k_owner_fast<4, PEXT>), dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
+    hipLaunchKernelGGL((k_owner_fast<4, PEXT, WIDE>), dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
                        ts, tile_fptr, tile_fine, TE, remap);
 }
 
@@ -328,10 +338,14 @@ hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const Ti
   if (tc.count == 0) return hipSuccess;
   const size_t lds = owner_fast_lds_bytes(TE, nw);
   const int remap = xcd_remap ? 1 : 0;
-  if (a.A_pext)
-    launch_fast_nw<true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+  if (a.A_pext && a.wide_a)
+    launch_fast_nw<true, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+  else if (a.A_pext)
+    launch_fast_nw<true, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+  else if (a.wide_a)
+    launch_fast_nw<false, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   else
-    launch_fast_nw<false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+    launch_fast_nw<false, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   return hipGetLastError();
 }
 

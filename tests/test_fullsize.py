@@ -117,6 +117,19 @@ def test_rows_beyond_one_thread_per_row_grid_cap():
     assert st["nnz_C"] == len(ref.col)
 
 
+def test_values_of_A_past_2GiB():
+    """216^3 27-point lognormal operator, 269,586,136 entries: A's values take 2.16 GB, beyond the
+    2 GiB a 32-bit buffer offset reaches, so the short-row owner kernel reads them by 64-bit
+    address.  The whole C against the oracle, for the default form and with the numeric cache."""
+    side = 216
+    A, P = gen.stencil27(side, seed=6), gen.trilinear(side)
+    assert A.nnz * 8 >= 2**31 and A.nnz * 4 < 2**31
+    ref = oracle.ptap(A, P)
+    g = GpuProblem(A, P)
+    _check_full(g, ref)
+    _check_full(g, ref, algo="merged", fold="owner", cache=True)
+
+
 @pytest.mark.parametrize("name", ["c3a", "c3b"])
 def test_c3_full_smoothed_aggregation(name):
     """Merged (owner fold), two-step (its short-row kernel walks the rows of P^T, up to 125
