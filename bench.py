@@ -78,6 +78,9 @@ def parse():
                     help="time only the two-step numeric on the workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of known size (counter calibration) and exit")
+    ap.add_argument("--size-sweep", type=int, nargs="+", metavar="SIDE",
+                    help="time the headline form (merged, owner fold, K = 1) on the 27-point "
+                         "lognormal workload at each fine grid side, one JSON line per side, and exit")
     return ap.parse_args()
 
 
@@ -108,6 +111,11 @@ def main():
 
     if args.fwd_bwd_only:
         print(json.dumps(fwd_bwd(lib, gen, torch, dev)))
+        return
+
+    if args.size_sweep:
+        for side in args.size_sweep:
+            print(json.dumps(size_point(lib, gen, torch, dev, side, args.steps)), flush=True)
         return
 
     t0 = time.time()
@@ -340,6 +348,29 @@ def _time_events(fn, reps, torch):
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def size_point(lib, gen, torch, dev, side, reps):
+    """The headline form at one fine grid side: numeric time by HIP events over `reps` numerics
+    after 3 warm-ups, and B / t."""
+    A, P = gen.stencil27(side, seed=1), gen.trilinear(side)
+    d = lambda a, t: torch.as_tensor(a, dtype=t, device=dev)  # noqa: E731
+    plan = lib.Plan(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
+                    d(P.rowptr, torch.int32), d(P.col, torch.int32), algo="merged", fold="owner")
+    Av, Pv = d(A.val, torch.float64), d(P.val, torch.float64)
+    C = plan.numeric(Av, Pv)
+    for _ in range(2):
+        plan.numeric(Av, Pv, C)
+    ms = _time_events(lambda: plan.numeric(Av, Pv, C), reps, torch)
+    st = plan.stats()
+    B = algorithmic_bytes(A.n_rows, A.nnz, P.nnz, st["nnz_C"])
+    out = {"side": side, "n": A.n_rows, "m": P.n_cols, "nnz_A": A.nnz, "nnz_P": P.nnz,
+           "nnz_C": st["nnz_C"], "numeric_ms": round(ms, 4), "GBps": round(B / ms / 1e6, 1),
+           "rows_formed_per_n": round(st["rows_formed"] / A.n_rows, 3), "n_tiles": st["n_tiles"]}
+    plan.close()
+    del C, Av, Pv
+    torch.cuda.empty_cache()
+    return out
 
 
 def sa_workloads(lib, gen, torch, dev):
