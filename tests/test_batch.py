@@ -134,6 +134,28 @@ def test_batch_with_general_tiles():
         p.close()
 
 
+@pytest.mark.slow
+def test_batch_with_A_values_past_2GiB():
+    """A 216^3 plan (269,586,136 entries of A: its values are read by 64-bit address) in one level
+    with three small plans: it is launched on its own inside the graph, the small ones through the
+    batched kernel, and every C matches the oracle."""
+    A = gen.stencil27(216, seed=7)
+    P = gen.trilinear(216)
+    assert A.nnz * 8 >= 2**31
+    probs = [GpuProblem(A, P)] + _independent(3, 4, 8, seed=6)
+    plans = [g.plan(algo="merged") for g in probs]
+    C = [torch.full((p.nnz_C,), np.nan, dtype=torch.float64, device="cuda") for p in plans]
+    batch = lib.Batch(plans)
+    batch.numeric([g.A_val for g in probs], [g.P_val for g in probs], C)
+    torch.cuda.synchronize()
+    for g, c in zip(probs, C):
+        ref = oracle.ptap(g.A, g.P)
+        assert_close(c.cpu().numpy(), ref.val, ref.abs)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_changed_pointers_and_bad_plans():
     probs = _independent(2, 4, 6, seed=9)
     plans = [g.plan(algo="merged") for g in probs]
