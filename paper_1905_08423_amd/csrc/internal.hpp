@@ -104,6 +104,8 @@ struct NumericArgs {
   // A's values span 2 GiB or more (nnz(A) >= 2^28): the short-row owner kernel reads them by
   // 64-bit address instead of a 32-bit buffer offset
   int wide_a;
+  // multiplier of the short-row owner kernel's R_I hash (odd; chosen per plan at symbolic time)
+  unsigned hash_mul;
 };
 hipError_t launch_pext(const Patterns& p, long long nnzA, int* out, hipStream_t s);
 

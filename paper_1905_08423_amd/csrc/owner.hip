@@ -155,6 +155,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   const Gather g{rA, rP, buffer_rsrc(p.A_col, nnzA * 4u), rPc, rPv, rAv,
                  buffer_rsrc(ts.slot, (unsigned)p.m * 4u), buffer_rsrc(a.A_pext, PEXT ? nnzA * 4u : 0u),
                  a.A_val};
+  const unsigned hmul = a.hash_mul;
   const int npass = a.part < 0 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int part = a.part < 0 ? (pass == 0 ? PART_OFF : PART_ON) : a.part;
@@ -204,10 +205,10 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
                           : ProdLoad{0, 0.0, 0.0, false};
 #pragma unroll
       for (int u = 0; u < kPrefetch; ++u)
-        if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v);
+        if (pq[u].ok) hash_add64(keys, vals, pq[u].j, pq[u].w * pq[u].v, hmul);
       for (int st = kPrefetch; st < nstep; ++st) {
         const ProdLoad cu = prod_load(st, incl, len, Th, sub, half, before, hs->rec[half], rPc, rPv);
-        if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v);
+        if (cu.ok) hash_add64(keys, vals, cu.j, cu.w * cu.v, hmul);
       }
       wave_sync();
       // (3) one load stage for each of the next two pairs.  Issued after the products' loads
@@ -241,7 +242,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
           const int c0 = kk < nsel ? rc.base : 0, c1 = kk < nsel ? rc.pad : 0;
           for (int c = c0 + sub; c < c1; c += kHalf) {
             const int j = tc[c];
-            const int s = hash_find64(keys, j);
+            const int s = hash_find64(keys, j, hmul);
             if (s >= 0) atomicAdd(tv + c, rc.w * vals[s]);
           }
         }

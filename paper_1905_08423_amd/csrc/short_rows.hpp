@@ -109,12 +109,17 @@ __device__ __forceinline__ ProdLoad prod_load(int st, int incl, int len, int Th,
   return r;
 }
 
+// Default multiplier of the 64-slot tables' hash (the top 6 bits of key * mul): the golden
+// ratio times 2^32.  The owner fold's short-row kernel takes a multiplier chosen per plan instead.
+constexpr unsigned kHashMul = 0x9E3779B1u;
+
 // R_I(key) += v in a 64-slot LDS table.  A plain read finds keys already present (most of a
 // row's products hit a key inserted before), so only first insertions use compare-and-swap.
 // The probe is bounded by the table size (a half never holds more than 32 keys, so the bound is
-// never reached).
-__device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v) {
-  unsigned s = hslot(key, kCapShift);
+// never reached).  Any odd multiplier gives the same result; it only moves keys between slots.
+__device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, double v,
+                                           unsigned mul = kHashMul) {
+  unsigned s = ((unsigned)key * mul) >> kCapShift;
 #pragma unroll 1  // rarely more than one probe: unrolling only adds exec-mask bookkeeping
   for (int it = 0; it < kCap; ++it) {
     int seen = keys[s];
@@ -130,8 +135,8 @@ __device__ __forceinline__ void hash_add64(int* keys, double* vals, int key, dou
 
 // Slot of key in a row's 64-slot table, or -1 (the table's inserts are complete).  Rolled: the
 // first read settles nearly every lookup.
-__device__ __forceinline__ int hash_find64(const int* keys, int key) {
-  unsigned s = hslot(key, kCapShift);
+__device__ __forceinline__ int hash_find64(const int* keys, int key, unsigned mul = kHashMul) {
+  unsigned s = ((unsigned)key * mul) >> kCapShift;
   int kf = keys[s];
 #pragma unroll 1
   for (int it = 1; kf != key && kf != EMPTY && it < kCap; ++it) {
