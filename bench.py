@@ -40,7 +40,8 @@ PROFILE = os.path.join(ROOT, "profiles", "owner_numeric_128cubed_27pt.md")
 # the kernel, and the host code and symbolic kernels that decide its tiles and their row order
 KERNEL_SOURCES = ["paper_1905_08423_amd/csrc/owner.hip", "paper_1905_08423_amd/csrc/short_rows.hpp",
                   "paper_1905_08423_amd/csrc/device.hpp", "paper_1905_08423_amd/csrc/internal.hpp",
-                  "paper_1905_08423_amd/csrc/kernels.hip", "paper_1905_08423_amd/csrc/api.cpp"]
+                  "paper_1905_08423_amd/csrc/kernels.hip", "paper_1905_08423_amd/csrc/api.cpp",
+                  "paper_1905_08423_amd/csrc/host_logic.hpp"]
 
 
 def profiled_traffic():

@@ -1,0 +1,191 @@
+// Host-side logic of the symbolic phase that needs no GPU: hash-table capacities, the owner tiles
+// and the hash multiplier of the short-row owner kernel.  Plain C++17: the library's host code
+// includes it, and so does a CPU test that checks these functions without a GPU.
+#pragma once
+
+#include <algorithm>
+#include <exception>
+#include <thread>
+#include <vector>
+
+namespace ptapk {
+namespace host {
+
+inline int next_pow2(long long v) {
+  long long c = 1;
+  while (c < v) c <<= 1;
+  return (int)std::min<long long>(c, 1LL << 30);
+}
+
+// Table capacity for a row whose key set has at most `need` distinct keys: a power of two of at
+// least 2*need slots (load factor <= 1/2), never below one slot per lane.
+inline int cap_for(long long need) { return std::max(64, next_pow2(2 * std::max(need, 1LL))); }
+
+// log2 of cap_for(need) for need >= 1: the smallest power of two >= 2*need, at least 64 and at
+// most 2^30.
+inline int cap_log2(long long need) {
+  const unsigned long long v = 2ULL * (unsigned long long)need;
+  const int b = v <= 64 ? 6 : 64 - __builtin_clzll(v - 1);
+  return std::min(b, 30);
+}
+
+// Tiles of rows of C for the owner fold, grown breadth-first over the graph of C's pattern (row
+// r is adjacent to the columns of row r): starting from the lowest unassigned row of the range
+// [lo, hi), rows of that range are taken in BFS order while the tile holds at most TE entries and
+// TR rows.  On meshes this gives compact tiles, so fewer fine rows touch two tiles than with
+// contiguous ranges of rows.  A row longer than TE forms a tile of its own (tglob = 1: kept in
+// device memory).  Rows within a tile are listed in ascending order.  Only state[lo..hi) is read
+// or written, so ranges can be grown at the same time.
+inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE, int TR, int* state,
+                std::vector<int>& tptr, std::vector<int>& trows, std::vector<char>& tglob) {
+  // state: -1 free, -2 queued for the tile being grown, >= 0 taken
+  std::vector<int> queue;
+  tptr.assign(1, 0);
+  trows.clear();
+  tglob.clear();
+  for (int seed = lo; seed < hi; ++seed) {
+    if (state[seed] != -1) continue;
+    const int T = (int)tglob.size();
+    if (cptr[seed + 1] - cptr[seed] > TE) {
+      state[seed] = T;
+      trows.push_back(seed);
+      tptr.push_back((int)trows.size());
+      tglob.push_back(1);
+      continue;
+    }
+    const size_t start = trows.size();
+    queue.clear();
+    queue.push_back(seed);
+    state[seed] = -2;
+    size_t head = 0;
+    long long acc = 0;
+    int nrows = 0;
+    while (head < queue.size()) {
+      const int r = queue[head];
+      const int sz = cptr[r + 1] - cptr[r];
+      if (acc + sz > TE || nrows >= TR) break;
+      ++head;
+      acc += sz;
+      ++nrows;
+      state[r] = T;
+      trows.push_back(r);
+      for (int k = cptr[r]; k < cptr[r + 1]; ++k) {
+        const int c = ccol[k];
+        if (c >= lo && c < hi && state[c] == -1) {
+          state[c] = -2;
+          queue.push_back(c);
+        }
+      }
+    }
+    for (size_t q = head; q < queue.size(); ++q) state[queue[q]] = -1;  // not taken
+    std::sort(trows.begin() + (long)start, trows.end());
+    tptr.push_back((int)trows.size());
+    tglob.push_back(0);
+  }
+}
+
+// Multiplier of the short-row owner kernel's R_I hash (slot = top 6 bits of key * mul, linear
+// probing over 64 slots).  The golden-ratio multiplier crowds the keys of some mesh sizes onto few
+// slots (a stencil row's keys are i + dx + dy s + dz s^2 for the grid side s), so candidates are
+// scored on a fixed sample of C's rows, which stand in for the rows R_I (both are sets of nearby
+// coarse columns): a row's columns inserted into an empty table, then the columns of the row of
+// its first column looked up, as the fold looks the columns of C's rows up in R_I.  The golden
+// ratio stays unless it needs more than 1.3 times the probes of the best candidate: it spreads
+// nearby keys evenly, which the probe count does not credit (simultaneous table accesses of a
+// half-wavefront meet less often), and measured at 128^3 a candidate with 8% fewer probes ran 9%
+// slower.  Candidates and sample are fixed (the candidates come from splitmix64 with a fixed
+// seed), so a plan gets the same multiplier on every machine.
+inline unsigned choose_hash_mul(int m, const std::vector<int>& cptr, const std::vector<int>& ccol) {
+  constexpr int kCands = 16, kSample = 512, kSlots = 64, kShift = 26, kMaxKeys = 32;
+  unsigned cand[kCands];
+  cand[0] = 0x9E3779B1u;
+  unsigned long long z = 0x243F6A8885A308D3ULL;
+  for (int c = 1; c < kCands; ++c) {
+    z += 0x9E3779B97F4A7C15ULL;
+    unsigned long long x = z;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    cand[c] = (unsigned)(x >> 32) | 1u;
+  }
+  const int S = std::min(m, kSample);
+  int keys[kSlots];
+  // probes to find `key` (or its empty slot, where an insert stores it)
+  auto probe = [&](int key, unsigned mul, bool insert) {
+    unsigned sl = ((unsigned)key * mul) >> kShift;
+    long long n = 1;
+    while (keys[sl] != -1 && keys[sl] != key) {
+      sl = (sl + 1) & (kSlots - 1);
+      ++n;
+    }
+    if (insert) keys[sl] = key;
+    return n;
+  };
+  long long best = -1, golden = 0;
+  unsigned pick = cand[0];
+  for (int c = 0; c < kCands; ++c) {
+    long long probes = 0;
+    for (int k = 0; k < S; ++k) {
+      const int r = (int)((long long)k * m / S);
+      const int b = cptr[r], e = cptr[r + 1];
+      if (e == b || e - b > kMaxKeys) continue;
+      std::fill(keys, keys + kSlots, -1);
+      for (int q = b; q < e; ++q) probes += probe(ccol[q], cand[c], true);
+      const int r2 = ccol[b];
+      for (int q = cptr[r2]; q < cptr[r2 + 1]; ++q) probes += probe(ccol[q], cand[c], false);
+    }
+    if (c == 0) golden = probes;
+    if (best < 0 || probes < best) {
+      best = probes;
+      pick = cand[c];
+    }
+  }
+  return golden * 10 > best * 13 ? pick : cand[0];
+}
+
+// All rows of C in tiles: the rows are split into up to kGrowParts contiguous ranges of at least
+// kGrowPartRows rows, grown on threads of their own, and the ranges' tiles listed in range order.
+// The split depends on m only, so the tiles are the same on every machine.
+constexpr int kGrowParts = 8;
+constexpr int kGrowPartRows = 32768;
+
+inline void grow_tiles(int m, const int* cptr, const int* ccol, int TE, int TR, std::vector<int>& tptr,
+                std::vector<int>& trows, std::vector<char>& tglob) {
+  const int parts = (int)std::max<long long>(1, std::min<long long>(kGrowParts, m / kGrowPartRows));
+  std::vector<int> state(m, -1);
+  std::vector<std::vector<int>> pp(parts), pr(parts);
+  std::vector<std::vector<char>> pg(parts);
+  std::vector<std::exception_ptr> err(parts);
+  auto work = [&](int p) {
+    try {
+      const int lo = (int)((long long)m * p / parts), hi = (int)((long long)m * (p + 1) / parts);
+      grow_range(lo, hi, cptr, ccol, TE, TR, state.data(), pp[p], pr[p], pg[p]);
+    } catch (...) {
+      err[p] = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  for (int p = 1; p < parts; ++p) {
+    try {
+      th.emplace_back(work, p);
+    } catch (...) {
+      work(p);  // no thread to spare: grow the range here
+    }
+  }
+  work(0);
+  for (std::thread& x : th) x.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  tptr.assign(1, 0);
+  trows.clear();
+  tglob.clear();
+  for (int p = 0; p < parts; ++p) {
+    const int base = (int)trows.size();
+    for (size_t k = 1; k < pp[p].size(); ++k) tptr.push_back(base + pp[p][k]);
+    trows.insert(trows.end(), pr[p].begin(), pr[p].end());
+    tglob.insert(tglob.end(), pg[p].begin(), pg[p].end());
+  }
+}
+
+}  // namespace host
+}  // namespace ptapk
