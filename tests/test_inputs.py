@@ -67,6 +67,23 @@ def test_seeded_determinism():
     assert a == b != c
 
 
+def test_one_dimensional_operator_and_single_node_aggregates():
+    """The inputs of the 17 M-row GPU test at a small size: laplacian7(n, 1, 1) is the tridiagonal
+    operator (diagonal 6, neighbours -1), and one damped-Jacobi step over single-node aggregates
+    gives P = I - (2/3) D^-1 A, tridiagonal and square: diagonal 1/3, neighbours 1/9."""
+    n = 50
+    A = gen.laplacian7(n, 1, 1)
+    A.check()
+    S = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(n, n)).toarray()
+    T = 6.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    assert A.nnz == 3 * n - 2 and np.array_equal(S, T)
+    P = gen.smoothed_aggregation(A, n, 1, 1, agg=1, steps=1)
+    P.check()
+    assert P.n_rows == n and P.n_cols == n and P.nnz == 3 * n - 2
+    D = sp.csr_matrix((P.val, P.col, P.rowptr), shape=(n, n)).toarray()
+    assert np.allclose(D, np.eye(n) / 3 + (np.eye(n, k=1) + np.eye(n, k=-1)) / 9, rtol=0, atol=1e-15)
+
+
 def test_smoothed_aggregation_row_lengths():
     s = 12
     A = gen.stencil27(s, seed=2, eps_z=0.01)
