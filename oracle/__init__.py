@@ -1,8 +1,10 @@
 """CPU oracle for C = P^T A P (test infrastructure only).
 
-The oracle is a plain single-threaded C implementation (ptap_oracle.c) of the definitions
-in Section 3 of the paper (Eq. allatonce, Eq. allatoncerow) and of the adjoint of
-Eq. tripleproduct.  It shares nothing with the GPU library.  Only the tests, the smoke
+The oracle is a plain C implementation (ptap_oracle.c) of the definitions in Section 3 of
+the paper (Eq. allatonce, Eq. allatoncerow) and of the adjoint of Eq. tripleproduct.  The
+product can split its output rows over threads (each row is computed the same way, so the
+result is bit-identical to one thread) and can accumulate in long double as a diagnostic of
+its own FP64 rounding.  It shares nothing with the GPU library.  Only the tests, the smoke
 check and the benchmark's CPU-baseline leg use it.
 
 Parity pins: see tests/test_oracle.py (dense products, Kronecker closed forms, boolean
@@ -26,7 +28,8 @@ _lib = None
 def build() -> str:
     """Compile the oracle with gcc (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"], check=True)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"],
+                   check=True)
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -49,6 +52,13 @@ def _bind(lib):
         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
         i32p, i32p, f64p, i32p, i32p, f64p, i32p, i32p, f64p,
         i32p, ctypes.c_int32, ctypes.c_int,
+        ctypes.POINTER(i32p), ctypes.POINTER(i32p), ctypes.POINTER(f64p), ctypes.POINTER(f64p),
+        ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_rap_ex.restype = ctypes.c_int
+    lib.oracle_rap_ex.argtypes = [
+        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+        i32p, i32p, f64p, i32p, i32p, f64p, i32p, i32p, f64p,
+        i32p, ctypes.c_int32, ctypes.c_int, ctypes.c_int32,
         ctypes.POINTER(i32p), ctypes.POINTER(i32p), ctypes.POINTER(f64p), ctypes.POINTER(f64p),
         ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_ptap_backward.restype = ctypes.c_int
@@ -109,8 +119,24 @@ def _arrays(M, need_val):
     return rp, c, v
 
 
-def rap(Q1, A, Q2, *, rows=None, pattern_only: bool = False) -> OracleResult:
-    """C = Q1^T A Q2 for CSR inputs (objects with n_rows, n_cols, rowptr, col, val)."""
+PATTERN_ONLY = 1
+LONG_DOUBLE = 2
+
+
+def cores() -> int:
+    """CPUs this process may run on (the thread count of the parallel oracle)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover - not Linux
+        return os.cpu_count() or 1
+
+
+def rap(Q1, A, Q2, *, rows=None, pattern_only: bool = False, long_double: bool = False,
+        threads: int = 1) -> OracleResult:
+    """C = Q1^T A Q2 for CSR inputs (objects with n_rows, n_cols, rowptr, col, val).
+
+    long_double: sum each row's terms in long double and round once (diagnostic).
+    threads: split the output rows over that many threads (bit-identical to one thread)."""
     lib = _load()
     n = A.n_rows
     if A.n_cols != n or Q1.n_rows != n or Q2.n_rows != n:
@@ -125,11 +151,15 @@ def rap(Q1, A, Q2, *, rows=None, pattern_only: bool = False) -> OracleResult:
     ov = ctypes.POINTER(ctypes.c_double)()
     oa = ctypes.POINTER(ctypes.c_double)()
     onnz = ctypes.c_int64()
-    rc = lib.oracle_rap(n, Q1.n_cols, Q2.n_cols, _ip(Arp), _ip(Ac), _dp(Av), _ip(Q1rp), _ip(Q1c),
-                        _dp(Q1v), _ip(Q2rp), _ip(Q2c), _dp(Q2v),
-                        _ip(sel) if sel is not None else None, 0 if sel is None else sel.size,
-                        1 if pattern_only else 0, ctypes.byref(orp), ctypes.byref(oc),
-                        ctypes.byref(ov), ctypes.byref(oa), ctypes.byref(onnz))
+    flags = (PATTERN_ONLY if pattern_only else 0) | (LONG_DOUBLE if long_double else 0)
+    args = (n, Q1.n_cols, Q2.n_cols, _ip(Arp), _ip(Ac), _dp(Av), _ip(Q1rp), _ip(Q1c), _dp(Q1v),
+            _ip(Q2rp), _ip(Q2c), _dp(Q2v), _ip(sel) if sel is not None else None,
+            0 if sel is None else sel.size)
+    outs = (ctypes.byref(orp), ctypes.byref(oc), ctypes.byref(ov), ctypes.byref(oa), ctypes.byref(onnz))
+    if flags == (PATTERN_ONLY if pattern_only else 0) and threads == 1:
+        rc = lib.oracle_rap(*args, 1 if pattern_only else 0, *outs)
+    else:
+        rc = lib.oracle_rap_ex(*args, flags, int(threads), *outs)
     if rc != 0:
         raise RuntimeError(f"oracle_rap failed ({rc})")
     nout = Q1.n_cols if sel is None else sel.size
@@ -148,9 +178,11 @@ def rap(Q1, A, Q2, *, rows=None, pattern_only: bool = False) -> OracleResult:
     return OracleResult(rowptr, col, val, absv, sel)
 
 
-def ptap(A, P, *, rows=None, pattern_only: bool = False) -> OracleResult:
+def ptap(A, P, *, rows=None, pattern_only: bool = False, long_double: bool = False,
+         threads: int = 1) -> OracleResult:
     """C = P^T A P (Section 3, Eq. tripleproduct), row form of Eq. allatonce."""
-    return rap(P, A, P, rows=rows, pattern_only=pattern_only)
+    return rap(P, A, P, rows=rows, pattern_only=pattern_only, long_double=long_double,
+               threads=threads)
 
 
 def ptap_backward(A, P, C_rowptr, C_col, W):

@@ -6,14 +6,16 @@
  * GPU library, and only the tests, the smoke check and the benchmark's CPU-baseline leg
  * may load it.
  *
- * Arithmetic: IEEE binary64, one thread, no blocking, no reordering beyond what the
- * definitions below state.
+ * Arithmetic: IEEE binary64 (a long double diagnostic mode exists for the product), no
+ * blocking, no reordering beyond what the definitions below state.  The product can split its
+ * output rows over threads; each row is computed the same way whichever thread runs it.
  *
  * Matrices are CSR with int32 row pointers and column indices (sorted, unique within a
  * row) and double values.  Every function returns 0 on success and a negative number on
  * an allocation failure or malformed input.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -119,44 +121,66 @@ void oracle_free(void* p) { free(p); }
  * Besides C the oracle returns, on the same pattern, Cabs = |Q1|^T |A| |Q2|, the sum of the
  * magnitudes of every product term, which bounds the rounding error of any summation order.
  *
- * rows / n_sel: if rows is NULL every output row 0..m1-1 is produced; otherwise only the
- * listed rows, in the listed order (out_rowptr then has n_sel+1 entries).
- * pattern_only: skip the values (out_val and out_abs are returned as NULL).
- *
- * Output arrays are allocated here with malloc and released with oracle_free.
+ * Every output row is computed on its own (the terms of row i, in the order above, into one
+ * accumulator per column), so splitting the rows over threads cannot change a single bit.
  */
-int oracle_rap(int32_t n, int32_t m1, int32_t m2, const int32_t* A_rowptr, const int32_t* A_col,
-               const double* A_val, const int32_t* Q1_rowptr, const int32_t* Q1_col,
-               const double* Q1_val, const int32_t* Q2_rowptr, const int32_t* Q2_col,
-               const double* Q2_val, const int32_t* rows, int32_t n_sel, int pattern_only,
-               int32_t** out_rowptr, int32_t** out_col, double** out_val, double** out_abs,
-               int64_t* out_nnz) {
-  ocsr Q1 = {n, m1, Q1_rowptr, Q1_col, Q1_val};
-  ocols q1c;
-  if (build_cols(&Q1, &q1c)) return -1;
-  int32_t nrows_out = rows ? n_sel : m1;
-  int32_t* rp = (int32_t*)malloc(((size_t)nrows_out + 1) * sizeof(int32_t));
-  double* acc = (double*)calloc((size_t)m2 + 1, sizeof(double));
-  double* absacc = (double*)calloc((size_t)m2 + 1, sizeof(double));
-  char* mark = (char*)calloc((size_t)m2 + 1, 1);
-  int32_t* touched = (int32_t*)malloc(((size_t)m2 + 1) * sizeof(int32_t));
-  obuf out = {0};
+
+/* Inputs and options shared by the row workers. */
+typedef struct {
+  int32_t m1, m2;
+  const int32_t *A_rowptr, *A_col;
+  const double* A_val;
+  const double* Q1_val;
+  const int32_t *Q2_rowptr, *Q2_col;
+  const double* Q2_val;
+  const ocols* q1c;
+  const int32_t* rows; /* NULL: output row r is row r of C */
+  int pattern_only;
+  int long_double;     /* accumulate in long double, round once at the end */
+} rap_job;
+
+/* Rows [r0, r1) of the output into out (columns, values, bounds) and len[r - r0] = the
+ * number of entries of row r.  Returns 0, -1 on allocation failure, -2 on a bad row index. */
+typedef struct {
+  const rap_job* job;
+  int32_t r0, r1;
+  int64_t* len;
+  obuf out;
+  int rc;
+} rap_part;
+
+static int rap_rows(rap_part* part) {
+  const rap_job* jb = part->job;
+  const ocols* q1c = jb->q1c;
+  const int pattern_only = jb->pattern_only;
+  const int32_t* A_rowptr = jb->A_rowptr;
+  const int32_t* A_col = jb->A_col;
+  const double* A_val = jb->A_val;
+  const double* Q1_val = jb->Q1_val;
+  const int32_t* Q2_rowptr = jb->Q2_rowptr;
+  const int32_t* Q2_col = jb->Q2_col;
+  const double* Q2_val = jb->Q2_val;
+  const size_t m2 = (size_t)jb->m2;
+  double* acc = (double*)calloc(m2 + 1, sizeof(double));
+  long double* accl = jb->long_double ? (long double*)calloc(m2 + 1, sizeof(long double)) : NULL;
+  double* absacc = (double*)calloc(m2 + 1, sizeof(double));
+  char* mark = (char*)calloc(m2 + 1, 1);
+  int32_t* touched = (int32_t*)malloc((m2 + 1) * sizeof(int32_t));
   int rc = 0;
-  if (!rp || !acc || !absacc || !mark || !touched) {
+  if (!acc || !absacc || !mark || !touched || (jb->long_double && !accl)) {
     rc = -1;
     goto done;
   }
-  rp[0] = 0;
-  for (int32_t r = 0; r < nrows_out; ++r) {
-    int32_t i = rows ? rows[r] : r;
-    if (i < 0 || i >= m1) {
+  for (int32_t r = part->r0; r < part->r1; ++r) {
+    int32_t i = jb->rows ? jb->rows[r] : r;
+    if (i < 0 || i >= jb->m1) {
       rc = -2;
       goto done;
     }
     int32_t ntouched = 0;
-    for (int32_t t = q1c.t_ptr[i]; t < q1c.t_ptr[i + 1]; ++t) {
-      int32_t I = q1c.t_row[t];
-      double w = pattern_only ? 0.0 : Q1_val[q1c.t_src[t]];
+    for (int32_t t = q1c->t_ptr[i]; t < q1c->t_ptr[i + 1]; ++t) {
+      int32_t I = q1c->t_row[t];
+      double w = pattern_only ? 0.0 : Q1_val[q1c->t_src[t]];
       for (int32_t ka = A_rowptr[I]; ka < A_rowptr[I + 1]; ++ka) {
         int32_t J = A_col[ka];
         double a = pattern_only ? 0.0 : A_val[ka];
@@ -166,37 +190,153 @@ int oracle_rap(int32_t n, int32_t m1, int32_t m2, const int32_t* A_rowptr, const
             mark[j] = 1;
             touched[ntouched++] = j;
           }
-          if (!pattern_only) {
-            double p = Q2_val[kp];
+          if (pattern_only) continue;
+          double p = Q2_val[kp];
+          if (accl)
+            accl[j] += (long double)w * ((long double)a * (long double)p);
+          else
             acc[j] += w * (a * p);
-            absacc[j] += fabs(w) * (fabs(a) * fabs(p));
-          }
+          absacc[j] += fabs(w) * (fabs(a) * fabs(p));
         }
       }
     }
     qsort(touched, (size_t)ntouched, sizeof(int32_t), cmp_i32);
     for (int32_t t = 0; t < ntouched; ++t) {
       int32_t j = touched[t];
-      if (obuf_push(&out, j, acc[j], absacc[j])) {
+      double v = accl ? (double)accl[j] : acc[j];
+      if (obuf_push(&part->out, j, v, absacc[j])) {
         rc = -1;
         goto done;
       }
       acc[j] = 0.0;
+      if (accl) accl[j] = 0.0L;
       absacc[j] = 0.0;
       mark[j] = 0;
     }
-    if (out.len > INT32_MAX) {
-      rc = -3;
-      goto done;
-    }
-    rp[r + 1] = (int32_t)out.len;
+    part->len[r - part->r0] = ntouched;
   }
 done:
-  free_cols(&q1c);
   free(acc);
+  free(accl);
   free(absacc);
   free(mark);
   free(touched);
+  part->rc = rc;
+  return rc;
+}
+
+static void* rap_thread(void* arg) {
+  rap_rows((rap_part*)arg);
+  return NULL;
+}
+
+/*
+ * rows / n_sel: if rows is NULL every output row 0..m1-1 is produced; otherwise only the
+ * listed rows, in the listed order (out_rowptr then has n_sel+1 entries).
+ * flags: ORACLE_PATTERN_ONLY skips the values (out_val and out_abs are returned as NULL);
+ * ORACLE_LONG_DOUBLE sums every row's terms in long double (x86 80-bit extended, 64-bit
+ * significand) and rounds each entry to double once, a diagnostic of the FP64 sums' own error.
+ * nthreads: the output rows are cut into that many contiguous ranges, one POSIX thread each;
+ * the result is identical bit for bit to nthreads = 1.
+ *
+ * Output arrays are allocated here with malloc and released with oracle_free.
+ */
+#define ORACLE_PATTERN_ONLY 1
+#define ORACLE_LONG_DOUBLE 2
+
+int oracle_rap_ex(int32_t n, int32_t m1, int32_t m2, const int32_t* A_rowptr, const int32_t* A_col,
+                  const double* A_val, const int32_t* Q1_rowptr, const int32_t* Q1_col,
+                  const double* Q1_val, const int32_t* Q2_rowptr, const int32_t* Q2_col,
+                  const double* Q2_val, const int32_t* rows, int32_t n_sel, int flags,
+                  int32_t nthreads, int32_t** out_rowptr, int32_t** out_col, double** out_val,
+                  double** out_abs, int64_t* out_nnz) {
+  const int pattern_only = (flags & ORACLE_PATTERN_ONLY) != 0;
+  ocsr Q1 = {n, m1, Q1_rowptr, Q1_col, Q1_val};
+  ocols q1c;
+  if (build_cols(&Q1, &q1c)) return -1;
+  int32_t nrows_out = rows ? n_sel : m1;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > nrows_out) nthreads = nrows_out > 0 ? nrows_out : 1;
+  rap_job job = {m1, m2, A_rowptr, A_col, A_val, Q1_val, Q2_rowptr, Q2_col, Q2_val, &q1c, rows,
+                 pattern_only, (flags & ORACLE_LONG_DOUBLE) != 0 && !pattern_only};
+  int32_t* rp = (int32_t*)malloc(((size_t)nrows_out + 1) * sizeof(int32_t));
+  int64_t* len = (int64_t*)calloc((size_t)nrows_out + 1, sizeof(int64_t));
+  rap_part* parts = (rap_part*)calloc((size_t)nthreads, sizeof(rap_part));
+  pthread_t* tid = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+  char* started = (char*)calloc((size_t)nthreads, 1);
+  obuf out = {0};
+  int rc = 0;
+  if (!rp || !len || !parts || !tid || !started) {
+    rc = -1;
+    goto done;
+  }
+  for (int32_t k = 0; k < nthreads; ++k) {
+    parts[k].job = &job;
+    parts[k].r0 = (int32_t)(((int64_t)nrows_out * k) / nthreads);
+    parts[k].r1 = (int32_t)(((int64_t)nrows_out * (k + 1)) / nthreads);
+    parts[k].len = len + parts[k].r0;
+  }
+  if (nthreads == 1) {
+    rap_rows(&parts[0]);
+  } else {
+    for (int32_t k = 0; k < nthreads; ++k)
+      started[k] = pthread_create(&tid[k], NULL, rap_thread, &parts[k]) == 0;
+    for (int32_t k = 0; k < nthreads; ++k) {
+      if (started[k])
+        pthread_join(tid[k], NULL);
+      else
+        rap_rows(&parts[k]); /* no thread could be started: run the range here */
+    }
+  }
+  /* concatenate the parts in row order */
+  int64_t total = 0;
+  for (int32_t k = 0; k < nthreads; ++k) {
+    if (parts[k].rc) {
+      rc = parts[k].rc;
+      goto done;
+    }
+    total += parts[k].out.len;
+  }
+  if (total > INT32_MAX) {
+    rc = -3;
+    goto done;
+  }
+  rp[0] = 0;
+  for (int32_t r = 0; r < nrows_out; ++r) rp[r + 1] = rp[r] + (int32_t)len[r];
+  if (nthreads == 1) {
+    out = parts[0].out;
+    parts[0].out = (obuf){0};
+  } else {
+    out.cap = total > 0 ? total : 1;
+    out.col = (int32_t*)malloc((size_t)out.cap * sizeof(int32_t));
+    out.val = (double*)malloc((size_t)out.cap * sizeof(double));
+    out.absv = (double*)malloc((size_t)out.cap * sizeof(double));
+    if (!out.col || !out.val || !out.absv) {
+      rc = -1;
+      goto done;
+    }
+    for (int32_t k = 0; k < nthreads; ++k) {
+      const obuf* b = &parts[k].out;
+      if (!b->len) continue;
+      memcpy(out.col + out.len, b->col, (size_t)b->len * sizeof(int32_t));
+      memcpy(out.val + out.len, b->val, (size_t)b->len * sizeof(double));
+      memcpy(out.absv + out.len, b->absv, (size_t)b->len * sizeof(double));
+      out.len += b->len;
+    }
+  }
+done:
+  free_cols(&q1c);
+  free(len);
+  free(tid);
+  free(started);
+  if (parts) {
+    for (int32_t k = 0; k < nthreads; ++k) {
+      free(parts[k].out.col);
+      free(parts[k].out.val);
+      free(parts[k].out.absv);
+    }
+    free(parts);
+  }
   if (rc) {
     free(rp);
     free(out.col);
@@ -222,6 +362,18 @@ done:
     *out_abs = out.absv;
   }
   return 0;
+}
+
+/* The product above in FP64 on one thread (pattern_only: skip the values). */
+int oracle_rap(int32_t n, int32_t m1, int32_t m2, const int32_t* A_rowptr, const int32_t* A_col,
+               const double* A_val, const int32_t* Q1_rowptr, const int32_t* Q1_col,
+               const double* Q1_val, const int32_t* Q2_rowptr, const int32_t* Q2_col,
+               const double* Q2_val, const int32_t* rows, int32_t n_sel, int pattern_only,
+               int32_t** out_rowptr, int32_t** out_col, double** out_val, double** out_abs,
+               int64_t* out_nnz) {
+  return oracle_rap_ex(n, m1, m2, A_rowptr, A_col, A_val, Q1_rowptr, Q1_col, Q1_val, Q2_rowptr,
+                       Q2_col, Q2_val, rows, n_sel, pattern_only ? ORACLE_PATTERN_ONLY : 0, 1,
+                       out_rowptr, out_col, out_val, out_abs, out_nnz);
 }
 
 /* Value of W(i, j) on the pattern of C, zero off it (binary search in row i). */

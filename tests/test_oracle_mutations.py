@@ -27,6 +27,14 @@ MUTATIONS = {
     "backward_sign_second_term": ("dP[kk] += s;", "dP[kk] -= s;"),
     "backward_transpose_W_in_dA": ("s += P_val[ki] * w_at(C_rowptr, C_col, W, i, j) * P_val[kj];",
                                    "s += P_val[ki] * w_at(C_rowptr, C_col, W, j, i) * P_val[kj];"),
+    # the long-double mode: a term rounded to double before it is added
+    "modes_long_double_rounds_terms": (
+        "accl[j] += (long double)w * ((long double)a * (long double)p);",
+        "accl[j] += (double)((long double)w * ((long double)a * (long double)p));"),
+    # the threaded mode: the last range of rows loses its last row to the next-to-last range
+    "modes_thread_ranges_shifted": (
+        "parts[k].r0 = (int32_t)(((int64_t)nrows_out * k) / nthreads);",
+        "parts[k].r0 = (int32_t)(((int64_t)nrows_out * k) / nthreads) + (k == nthreads - 1 && k > 0);"),
 }
 
 
@@ -37,7 +45,8 @@ def _build_mutant(tmp_path, name):
     src = tmp_path / f"{name}.c"
     src.write_text(text.replace(old, new))
     lib = tmp_path / f"{name}.so"
-    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", str(lib), str(src), "-lm"], check=True)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", str(lib), str(src), "-lm"],
+                   check=True)
     return str(lib)
 
 
@@ -86,14 +95,32 @@ def _backward_pins_pass():
     return bool(close_mask(dA, gA, bA).all() and close_mask(dP, gP, bP).all())
 
 
+def _modes_pins_pass():
+    """The pins of the long-double and threaded modes (tests/test_oracle_modes.py)."""
+    import test_oracle_modes as tm
+
+    try:
+        tm.test_long_double_is_exact_sum_correctly_rounded(21)
+        tm.test_threads_bit_identical("stencil27_lognormal_24", 3)
+    except AssertionError:
+        return False
+    return True
+
+
 def test_unmutated_oracle_passes_the_subset():
     assert _forward_pins_pass()
     assert _backward_pins_pass()
+    assert _modes_pins_pass()
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_pins_catch_mutation(tmp_path, name):
     lib = _build_mutant(tmp_path, name)
     with oracle.use_library(lib):
-        caught = (not _forward_pins_pass()) if not name.startswith("backward") else (not _backward_pins_pass())
+        if name.startswith("backward"):
+            caught = not _backward_pins_pass()
+        elif name.startswith("modes"):
+            caught = not _modes_pins_pass()
+        else:
+            caught = not _forward_pins_pass()
     assert caught, f"planted mistake {name} was not caught"
