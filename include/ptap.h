@@ -63,14 +63,23 @@ typedef enum ptap_fold {
   PTAP_FOLD_AUTO = 0,   /* the owner fold (the faster one on MI355X) */
   PTAP_FOLD_ATOMIC = 1, /* fine-row sweep; device-wide FP64 atomic adds into C at the slot of
                            each (i, j), found through C's column list of row i */
-  PTAP_FOLD_OWNER = 2   /* coarse-row ownership: a workgroup owns a contiguous tile of C rows,
-                           visits the fine rows I with P(I,i) stored for i in the tile (found
-                           through P's column index lists, i.e. Eq. allatoncerow), forms each
-                           R_I and accumulates in on-chip memory; no global atomics */
+  PTAP_FOLD_OWNER = 2   /* coarse-row ownership: a workgroup owns a tile of C rows (grown
+                           breadth-first over C's pattern at symbolic time), visits the fine
+                           rows I with P(I,i) stored for i in the tile (found through P's column
+                           index lists, i.e. Eq. allatoncerow), forms each R_I and accumulates
+                           the tile in LDS, written to C once.  A row of C longer than a tile is
+                           accumulated in C itself with device atomics.  The wavefronts of a
+                           workgroup add into the tile in the order they arrive, so results on
+                           non-dyadic values can differ in the last bits between runs (every
+                           order is a valid FP64 evaluation of the same sum). */
 } ptap_fold;
 
 /* Allocator for device workspace.  alloc returns a device pointer or NULL; release frees a
- * pointer returned by alloc.  ctx is passed through unchanged. */
+ * pointer returned by alloc.  ctx is passed through unchanged.  Releases are stream-ordered: the
+ * library may call release right after enqueueing, on the plan's stream, the last launch that
+ * uses the pointer, so release must not let the memory be reused before the work already
+ * enqueued on that stream has finished (stream-ordered allocators and caching allocators that
+ * track the stream do this; a plain hipFree waits for the device). */
 typedef struct ptap_allocator {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*release)(void* ptr, size_t bytes, void* ctx);
@@ -104,7 +113,15 @@ typedef struct ptap_options {
                             looking the row pointers of P up again in every numeric.  Built only
                             when the owner fold uses that kernel and nnz(P) < 2^26; the bytes
                             held are reported in ptap_stats.cache_bytes. */
-  int32_t reserved[5];
+  int32_t owner_kernel;  /* owner fold, merged form (and all-at-once with K = 1): 0 = the
+                            short-row and general owner kernels (default); 1 = staged tiles where
+                            they fit: the tile's workgroup first copies the rows P(J,:) that its
+                            fine rows read (the halo: the columns of A(I,:) over the tile's fine
+                            rows I, and the rows I) into LDS, then forms each R_I from there
+                            (Eq. allatoncerow).  The halo lists cost 4 bytes per halo row per
+                            tile, held by the plan (ptap_stats.workspace_bytes); tiles whose halo
+                            does not fit in LDS use the other kernels. */
+  int32_t reserved[4];
 } ptap_options;
 
 typedef struct ptap_stats {
@@ -122,7 +139,11 @@ typedef struct ptap_stats {
   int32_t nblocks;
   int64_t cache_bytes;         /* device bytes of the numeric cache (ptap_options.cache); else 0 */
   int64_t block_size;          /* bs of a block-sparse plan (ptap_plan_create_bsr); else 1 */
-  int64_t reserved[6];
+  int64_t staged_tiles;        /* owner fold: tiles that take the staged-tile kernel */
+  int64_t staged_lds_bytes;    /* LDS bytes per workgroup of that kernel's launch (0: none) */
+  int64_t table_slots;         /* device-memory hash-table slots the general kernels use (rows
+                                  whose tables do not fit in LDS); 0 when every table is in LDS */
+  int64_t reserved[3];
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;
@@ -180,6 +201,15 @@ ptap_status ptap_get_pattern(const ptap_plan* plan, int64_t* nnz_C, const int32_
                              const int32_t** C_col);
 
 /*
+ * Copy the pattern of C into caller-owned device buffers: C_rowptr (m + 1 entries) and C_col
+ * (nnz(C) entries), asynchronously on the stream (device-to-device).  Either pointer may be NULL
+ * to skip that array.  The plan keeps its own copy.  Errors: PTAP_ERR_INPUT (NULL plan),
+ * PTAP_ERR_STATE before symbolic, PTAP_ERR_HIP.
+ */
+ptap_status ptap_copy_pattern(const ptap_plan* plan, int32_t* C_rowptr, int32_t* C_col,
+                              hipStream_t stream);
+
+/*
  * Numeric phase (Alg. 8 all-at-once, Alg. 10 merged, Alg. 6 two-step): writes the nnz(C)
  * values of C, in the order of the pattern, into the caller's device array C_val.  A_val and
  * P_val hold the values of A and P in the order of their patterns.  Asynchronous on the
@@ -201,7 +231,10 @@ ptap_status ptap_backward(ptap_plan* plan, const double* A_val, const double* P_
                           const double* dC_val, double* dA_val, double* dP_val,
                           hipStream_t stream);
 
-/* Statistics of the plan (host struct filled by the call). */
+/* Statistics of the plan (host struct filled by the call): the device memory the plan holds and
+ * its high-water mark (the counterpart of the "Mem" column of Section 4's tables, which reports
+ * the memory of each algorithm), and the work one numeric call does (rows of AP formed, with
+ * recomputation, against the rows needed; fold terms).  Errors: PTAP_ERR_INPUT (NULL). */
 ptap_status ptap_plan_stats(const ptap_plan* plan, ptap_stats* out);
 
 /* Release the plan and all its device workspace (through the plan's allocator).  Accepts

@@ -124,11 +124,16 @@ LONG_DOUBLE = 2
 
 
 def cores() -> int:
-    """CPUs this process may run on (the thread count of the parallel oracle)."""
+    """Threads for the parallel oracle: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when that is set (a host shared between jobs sets it to this job's share)."""
     try:
-        return len(os.sched_getaffinity(0))
+        n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover - not Linux
-        return os.cpu_count() or 1
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
 
 
 def rap(Q1, A, Q2, *, rows=None, pattern_only: bool = False, long_double: bool = False,

@@ -45,7 +45,7 @@ class ptap_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("backward", ctypes.c_int32), ("owner_waves", ctypes.c_int32),
                 ("tile_lds", ctypes.c_int32), ("cache", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("owner_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class ptap_stats(ctypes.Structure):
@@ -56,7 +56,8 @@ class ptap_stats(ctypes.Structure):
                 ("n_tiles", ctypes.c_int32), ("fold_used", ctypes.c_int32),
                 ("algo", ctypes.c_int32), ("nblocks", ctypes.c_int32),
                 ("cache_bytes", ctypes.c_int64), ("block_size", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("staged_tiles", ctypes.c_int64), ("staged_lds_bytes", ctypes.c_int64),
+                ("table_slots", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -74,6 +75,7 @@ _SIGNATURES = {
                                             _vp]),
     "ptap_symbolic": (ctypes.c_int, [_vp, _vp]),
     "ptap_get_pattern": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "ptap_copy_pattern": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ptap_numeric": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptap_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptap_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ptap_stats)]),
@@ -182,6 +184,10 @@ def ptap_get_pattern(plan):
     return st, nnz.value, rp.value, col.value
 
 
+def ptap_copy_pattern(plan, C_rowptr, C_col, stream=None):
+    return load_library().ptap_copy_pattern(plan, _ptr(C_rowptr), _ptr(C_col), _stream(stream))
+
+
 def ptap_numeric(plan, A_val, P_val, C_val, stream=None):
     return load_library().ptap_numeric(plan, _ptr(A_val), _ptr(P_val), _ptr(C_val), _stream(stream))
 
@@ -243,8 +249,15 @@ def stream_sum(x, out=None, stream=None):
 # see the plan's workspace.
 # ---------------------------------------------------------------------------------------------
 class TorchAllocator:
-    def __init__(self, device=None):
+    """The library releases a buffer as soon as it has enqueued the last launch that uses it, so
+    a release is stream-ordered: the tensor is marked as used on the plan's stream
+    (record_stream) before it is dropped, and torch's caching allocator does not hand the block
+    to another stream until that work is done.  Without an explicit stream the plan runs on
+    torch's current stream, where torch already orders reuse."""
+
+    def __init__(self, device=None, stream=None):
         self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.stream = stream if isinstance(stream, torch.cuda.Stream) else None
         self.live = {}
         alloc_t = ptap_allocator._fields_[0][1]
         release_t = ptap_allocator._fields_[1][1]
@@ -258,7 +271,9 @@ class TorchAllocator:
             return t.data_ptr()
 
         def _release(ptr, nbytes, ctx):
-            self.live.pop(ptr, None)
+            t = self.live.pop(ptr, None)
+            if t is not None and self.stream is not None:
+                t.record_stream(self.stream)
 
         self.c_alloc = alloc_t(_alloc)
         self.c_release = release_t(_release)
@@ -279,14 +294,14 @@ class Plan:
 
     def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
                  nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
-                 backward=False, owner_waves=0, tile_lds=0, cache=False, block_size=1, allocator=None,
-                 stream=None):
+                 backward=False, owner_waves=0, tile_lds=0, cache=False, staged=False, block_size=1,
+                 allocator=None, stream=None):
         load_library()
         self.n, self.m = int(n), int(m)
         self.A_rowptr, self.A_col = A_rowptr, A_col
         self.P_rowptr, self.P_col = P_rowptr, P_col
         self.A_nnz, self.P_nnz = int(A_col.numel()), int(P_col.numel())
-        self.allocator = allocator if allocator is not None else TorchAllocator(A_rowptr.device)
+        self.allocator = allocator if allocator is not None else TorchAllocator(A_rowptr.device, stream)
         o = ptap_options_default()
         o.algo = ALGOS[algo] if isinstance(algo, str) else int(algo)
         o.fold = FOLDS[fold] if isinstance(fold, str) else int(fold)
@@ -299,6 +314,7 @@ class Plan:
         o.owner_waves = int(owner_waves)
         o.tile_lds = int(tile_lds)
         o.cache = 1 if cache else 0
+        o.owner_kernel = 1 if staged else 0
         self.options = o
         self.handle = None
         self.bs = int(block_size)
@@ -329,10 +345,7 @@ class Plan:
         """(C_rowptr, C_col) as new int32 device tensors (copies of the plan-owned arrays)."""
         rp = torch.empty(self.m + 1, dtype=torch.int32, device=self.A_rowptr.device)
         col = torch.empty(max(self.nnz_C, 0), dtype=torch.int32, device=self.A_rowptr.device)
-        if self.m + 1:
-            _memcpy_d2d(rp, self._rp_ptr, (self.m + 1) * 4)
-        if self.nnz_C:
-            _memcpy_d2d(col, self._col_ptr, self.nnz_C * 4)
+        _check(ptap_copy_pattern(self.handle, rp, col if self.nnz_C else None), "ptap_copy_pattern")
         return rp, col
 
     def numeric(self, A_val, P_val, C_val=None, stream=None):
@@ -370,32 +383,6 @@ class Plan:
             pass
 
 
-def _memcpy_d2d(dst_tensor, src_ptr, nbytes):
-    """Device-to-device copy of a plan-owned array into a tensor, on the current stream (torch
-    has no tensor-from-pointer API, so this calls hipMemcpyAsync of the loaded HIP runtime)."""
-    hip = _hip()
-    rc = hip.hipMemcpyAsync(ctypes.c_void_p(dst_tensor.data_ptr()), ctypes.c_void_p(src_ptr),
-                            ctypes.c_size_t(nbytes), ctypes.c_int(3),
-                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-    if rc != 0:
-        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
-
-
-_hip_lib = None
-
-
-def _hip():
-    global _hip_lib
-    if _hip_lib is None:
-        # the HIP runtime torch has already loaded into this process
-        torch_lib = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
-        _hip_lib = ctypes.CDLL(torch_lib if os.path.exists(torch_lib) else "libamdhip64.so")
-        _hip_lib.hipMemcpyAsync.restype = ctypes.c_int
-        _hip_lib.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
-                                            ctypes.c_int, ctypes.c_void_p]
-    return _hip_lib
-
-
 class Batch:
     """Batched numeric products over several plans (Plan objects) in one HIP graph.
 
@@ -406,7 +393,7 @@ class Batch:
 
     def __init__(self, plans, levels=None, allocator=None, stream=None):
         self.plans = list(plans)
-        self.allocator = allocator if allocator is not None else TorchAllocator()
+        self.allocator = allocator if allocator is not None else TorchAllocator(stream=stream)
         st, h = ptap_batch_create([p.handle for p in self.plans], levels, self.allocator.struct, stream)
         _check(st, "ptap_batch_create")
         self.handle = h

@@ -214,6 +214,12 @@ struct ptap_plan {
   std::vector<int> host_fptr;
   std::vector<TileClass> tclasses;
   bool any_tile_global = false;
+  // staged-tile kernel: the tiles that take it, their halo rows and the launch's LDS layout
+  int* staged_tiles = nullptr;
+  int n_staged = 0;
+  int* halo_ptr = nullptr;
+  int* halo_rows = nullptr;
+  StagedLayout staged_L{};
   bool wide_a = false;  // A's values pass 2 GiB: the short-row owner kernel reads them by address
   unsigned hash_mul = 0x9E3779B1u;  // the short-row owner kernel's R_I hash multiplier
 
@@ -239,9 +245,10 @@ struct ptap_plan {
   // adjoint
   std::vector<RowClass> bwd_rows;
 
-  // spill tables for numeric / adjoint launches
+  // spill tables for numeric / adjoint launches (spill_slots keys and as many values)
   int* gtab = nullptr;
   double* gval = nullptr;
+  size_t spill_slots = 0;
 
   // numeric cache (options.cache): packed extent of the row of P selected by each entry of A
   int* A_pext = nullptr;
@@ -337,6 +344,7 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
   if (o.algo < PTAP_ALLATONCE || o.algo > PTAP_TWOSTEP) return PTAP_ERR_INPUT;
   if (o.fold < PTAP_FOLD_AUTO || o.fold > PTAP_FOLD_OWNER) return PTAP_ERR_INPUT;
   if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0 || o.tile_lds < 0) return PTAP_ERR_INPUT;
+  if (o.owner_kernel < 0 || o.owner_kernel > 1) return PTAP_ERR_INPUT;
   if (o.owner_waves != 0 && o.owner_waves != 4 && o.owner_waves != 8 && o.owner_waves != 16)
     return PTAP_ERR_INPUT;
   if (o.hash_slots && (o.hash_slots < 64 || (o.hash_slots & (o.hash_slots - 1)))) return PTAP_ERR_INPUT;
@@ -708,13 +716,21 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         room = ((long long)lds_tile - (long long)kWavesPerBlock * ((long long)sizeof(WaveScratch) + (long long)cap_all * 12) -
                 (TR + 1) * 4LL - 16) / 12;
       int TE = (int)std::max<long long>(16, room);
+      // the staged-tile kernel (merged or one-block forms, A's values within 2 GiB) holds a tile's
+      // halo rows of P beside the tile: smaller tiles, one workgroup per CU
+      const bool twopass_owner = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+      int crow_max = 0;
+      for (int i = 0; i < m; ++i) crow_max = std::max(crow_max, h_c_ptr[i + 1] - h_c_ptr[i]);
+      const bool staging = P->opt.owner_kernel == 1 && !twopass_owner && fast_fits && !P->wide_a &&
+                           !P->opt.cache && crow_max <= kStagedMaxRank;
+      if (staging && !P->opt.tile_lds) TE = std::min(TE, kStagedTileEntries);
       if (P->opt.tile_entries) {
         TE = std::min(TE, (int)P->opt.tile_entries);
       } else if (!P->opt.tile_lds) {
         // Fewer tiles than resident workgroups (two per CU) leave CUs idle: shrink the tiles until
         // they fill about 95% of one round of workgroups (not more, or a few tiles run alone in
         // a second round), accepting the extra rows of AP that smaller tiles form twice.
-        const long long slots = 2LL * P->n_cu;
+        const long long slots = (staging ? 1LL : 2LL) * P->n_cu;
         if (P->nnzC / TE < slots) {
           const long long te_par = (P->nnzC * 100) / (95 * slots);
           TE = (int)std::min<long long>(TE, std::max<long long>(te_par, 256));
@@ -784,10 +800,84 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
                                P->off_fptr, P->off_fine, PART_OFF, P->opt.nblocks, s));
         P->rows_formed += oacc;
       }
+      // staged tiles: halo sizes of every tile on the device, then the tiles that fit one launch
+      std::vector<char> is_staged(T, 0);
+      if (staging) {
+        std::vector<int> all(T);
+        for (int k = 0; k < T; ++k) all[k] = k;
+        int* d_all = t.get<int>(T);
+        to_device(d_all, all, s);
+        int* st = t.get<int>(6 * (size_t)T);
+        hipck(launch_tile_halo(pat, d_all, T, P->tile_fptr, P->tile_fine, false, st, nullptr,
+                               nullptr, s));
+        const std::vector<int> hs = to_host(st, 6 * (size_t)T, s);
+        t.put(st);
+        // candidate tiles and their own LDS needs
+        std::vector<std::pair<size_t, int>> cand;
+        std::vector<StagedCaps> caps(T);
+        for (int k = 0; k < T; ++k) {
+          const int* o = &hs[6 * (size_t)k];
+          const int nrk = tptr[k + 1] - tptr[k];
+          int rowmax = 0, te = 0;
+          for (int q = tptr[k]; q < tptr[k + 1]; ++q) {
+            const int len = h_c_ptr[trows[q] + 1] - h_c_ptr[trows[q]];
+            rowmax = std::max(rowmax, len);
+            te += len;
+          }
+          const bool ok = !tglob[k] && o[5] == 0 && o[0] <= kStagedMaxHalo && o[2] <= kStagedMaxCols &&
+                          o[3] <= kStagedMaxA && o[4] <= kStagedMaxP && rowmax <= kStagedMaxRank &&
+                          nrk <= kStagedMaxRows && o[1] < (1 << 24) && te < 65536;
+          if (!ok) continue;
+          caps[k] = StagedCaps{nrk, std::max(te, 1), std::max(o[0], 1), std::max(o[1], 1), std::max(o[2], 1)};
+          cand.emplace_back(staged_layout(caps[k], kStagedWaves, nullptr), k);
+        }
+        // the launch's layout takes the maxima over its tiles: drop the largest tiles until it fits
+        std::sort(cand.begin(), cand.end());
+        const size_t limit = (size_t)P->lds_device - 256;  // the kernel's own LDS variables
+        size_t keep = cand.size();
+        StagedCaps cm{1, 1, 1, 1, 1};
+        while (keep > 0) {
+          cm = StagedCaps{1, 1, 1, 1, 1};
+          for (size_t x = 0; x < keep; ++x) {
+            const StagedCaps& c = caps[cand[x].second];
+            cm.NR = std::max(cm.NR, c.NR);
+            cm.TE = std::max(cm.TE, c.TE);
+            cm.NH = std::max(cm.NH, c.NH);
+            cm.SE = std::max(cm.SE, c.SE);
+            cm.UL = std::max(cm.UL, c.UL);
+          }
+          if (staged_layout(cm, kStagedWaves, nullptr) <= limit) break;
+          keep = keep * 31 / 32;
+        }
+        if (keep > 0) {
+          staged_layout(cm, kStagedWaves, &P->staged_L);
+          std::vector<int> stl, hptr(T + 1, 0);
+          for (size_t x = 0; x < keep; ++x) is_staged[cand[x].second] = 1;
+          long long hacc = 0;
+          for (int k = 0; k < T; ++k) {
+            if (is_staged[k]) {
+              stl.push_back(k);
+              hacc += hs[6 * (size_t)k];
+            }
+            if (hacc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
+            hptr[k + 1] = (int)hacc;
+          }
+          P->n_staged = (int)stl.size();
+          P->staged_tiles = t.get<int>(stl.size());
+          to_device(P->staged_tiles, stl, s);
+          P->halo_ptr = t.get<int>(T + 1);
+          to_device(P->halo_ptr, hptr, s);
+          P->halo_rows = t.get<int>(std::max<long long>(hacc, 1));
+          hipck(launch_tile_halo(pat, P->staged_tiles, P->n_staged, P->tile_fptr, P->tile_fine, true,
+                                 nullptr, P->halo_ptr, P->halo_rows, s));
+        }
+        t.put(d_all);
+      }
       // classes by (kernel, hash capacity, placement); a tile with no fine row still runs so that
       // its (empty) rows are written
       std::map<std::tuple<int, int, int>, std::vector<int>> groups;
       for (int k = 0; k < T; ++k) {
+        if (is_staged[k]) continue;
         const int rm = hrmax[2 * k], lm = hrmax[2 * k + 1];
         const bool fast = fast_fits && !tglob[k] && rm <= kFastMaxKeys && lm <= kFastMaxKeys &&
                           owner_fast_lds_bytes(TE, nw) <= (size_t)P->lds_device;
@@ -880,6 +970,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   }
 
   t.put(r);
+  P->spill_slots = std::max(spill_need_ints, spill_need_vals);
   if (spill_need_ints) P->gtab = t.get<int>(spill_need_ints);
   if (spill_need_vals) P->gval = t.get<double>(spill_need_vals);
   if (P->gtab) hipck(launch_fill_i32(P->gtab, EMPTY, (long long)spill_need_ints, s));
@@ -920,6 +1011,23 @@ ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream) {
   return PTAP_OK;
 }
 
+ptap_status ptap_copy_pattern(const ptap_plan* plan, int32_t* C_rowptr, int32_t* C_col,
+                              hipStream_t stream) {
+  if (!plan) return PTAP_ERR_INPUT;
+  if (!plan->sym_done) return PTAP_ERR_STATE;
+  try {
+    if (C_rowptr)
+      hipck(hipMemcpyAsync(C_rowptr, plan->C_rowptr, ((size_t)plan->pat.m + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, stream));
+    if (C_col && plan->nnzC)
+      hipck(hipMemcpyAsync(C_col, plan->C_col, (size_t)plan->nnzC * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, stream));
+  } catch (...) {
+    return caught_status();
+  }
+  return PTAP_OK;
+}
+
 ptap_status ptap_get_pattern(const ptap_plan* plan, int64_t* nnz_C, const int32_t** C_rowptr,
                              const int32_t** C_col) {
   if (!plan) return PTAP_ERR_INPUT;
@@ -949,13 +1057,12 @@ static NumericArgs numeric_args(ptap_plan* P, const double* A_val, const double*
   return a;
 }
 
-ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val, double* C_val,
-                         hipStream_t s) {
-  if (!P) return PTAP_ERR_INPUT;
-  if (!P->sym_done) return PTAP_ERR_STATE;
-  if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!C_val && P->nnzC)) return PTAP_ERR_INPUT;
-  try {
-    if (P->nnzC == 0) return PTAP_OK;
+// The numeric phase with the device-memory hash tables of the general kernels at gtab / gval
+// (the plan's own workspace, or the static scratch of ptap_numeric_noalloc).  Throws Failure.
+static void numeric_impl(ptap_plan* P, const double* A_val, const double* P_val, double* C_val,
+                         int* gtab, double* gval, hipStream_t s) {
+  {
+    if (P->nnzC == 0) return;
     if (P->bs > 1) {
       const BsrArgs b{P->pat.A_rowptr, P->pat.A_col, P->pat.P_rowptr, P->pat.P_col, A_val, P_val,
                       P->C_rowptr, P->C_col, C_val, P->pt_ptr, P->pt_row, P->pt_pos};
@@ -964,12 +1071,12 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
                                P->opt.xcd_remap != 0, s));
       hipck(launch_bsr_numeric(b, P->bs, P->bsr_rows_glob, P->bsr_n_glob, 64, 0, false,
                                P->opt.xcd_remap != 0, s));
-      return PTAP_OK;
+      return;
     }
     if (P->opt.algo == PTAP_TWOSTEP) {
       NumericArgs a = numeric_args(P, A_val, P_val, C_val, PART_ALL);
       for (auto& c : P->ap_rows)
-        hipck(launch_ap_numeric(a, c, P->AP_rowptr, P->AP_col, P->AP_val, P->gtab, P->gval, s));
+        hipck(launch_ap_numeric(a, c, P->AP_rowptr, P->AP_col, P->AP_val, gtab, gval, s));
       const RowMulArgs g1{P->pat.A_rowptr, P->pat.A_col, A_val, P->pat.P_rowptr, P->pat.P_col,
                           P_val, P->AP_rowptr, P->AP_col, P->AP_val, P->pat.n, P->pat.n,
                           P->nnzA, P->nnzP, P->nnzAP};
@@ -978,13 +1085,13 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
       hipck(launch_gather(P_val, P->pt_pos, P->PT_val, P->nnzP, s));
       for (auto& c : P->ptc_rows)
         hipck(launch_ptc_numeric(P->pt_ptr, P->pt_row, P->PT_val, P->AP_rowptr, P->AP_col,
-                                 P->AP_val, P->C_rowptr, P->C_col, C_val, c, P->gtab, P->gval, s));
+                                 P->AP_val, P->C_rowptr, P->C_col, C_val, c, gtab, gval, s));
       const RowMulArgs g2{P->pt_ptr, P->pt_row, P->PT_val, P->AP_rowptr, P->AP_col, P->AP_val,
                           P->C_rowptr, P->C_col, C_val, P->pat.m, P->pat.n,
                           P->nnzP, P->nnzAP, P->nnzC};
       for (int k = 0; k < 2; ++k)
         hipck(launch_rowmul_short(g2, P->ptc_short[k], P->n_ptc_short[k], k == 1, P->n_cu, s));
-      return PTAP_OK;
+      return;
     }
     const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
     if (P->fold_used == PTAP_FOLD_ATOMIC) {
@@ -992,17 +1099,22 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
       const int parts[2] = {twopass ? PART_OFF : PART_ALL, PART_ON};
       for (int k = 0; k < (twopass ? 2 : 1); ++k) {
         NumericArgs a = numeric_args(P, A_val, P_val, C_val, parts[k]);
-        for (auto& c : P->arows) hipck(launch_atomic_numeric(a, c, P->gtab, P->gval, s));
+        for (auto& c : P->arows) hipck(launch_atomic_numeric(a, c, gtab, gval, s));
       }
       RowMulArgs gf{P->pat.A_rowptr, P->pat.A_col, A_val, P->pat.P_rowptr, P->pat.P_col, P_val,
                     P->pat.P_rowptr, P->pat.P_col, nullptr, P->pat.n, P->pat.n, P->nnzA,
                     P->nnzP, P->nnzP, P_val, P->C_rowptr, P->C_col, C_val, P->pat.m, P->nnzC};
       for (int k = 0; k < 2; ++k)
         hipck(launch_atomic_fold_short(gf, P->af_short[k], P->n_af_short[k], k == 1, P->n_cu, s));
-      return PTAP_OK;
+      return;
     }
     if (P->any_tile_global) hipck(launch_fill_f64(C_val, 0.0, P->nnzC, s));
     NumericArgs a = numeric_args(P, A_val, P_val, C_val, twopass ? -1 : PART_ALL);
+    if (P->n_staged) {
+      const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
+      hipck(launch_staged(a, P->staged_tiles, P->n_staged, ts, P->tile_fptr, P->tile_fine, P->halo_ptr,
+                          P->halo_rows, P->staged_L, P->opt.xcd_remap != 0, s));
+    }
     for (auto& c : P->tclasses) {
       const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
       if (c.fast)
@@ -1010,11 +1122,20 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
                                 P->opt.xcd_remap != 0, s));
       else
         hipck(launch_owner_numeric(a, c, ts, P->tile_fptr, P->tile_fine, P->TE,
-                                   P->opt.xcd_remap != 0, P->gtab, P->gval, s));
+                                   P->opt.xcd_remap != 0, gtab, gval, s));
     }
+  }
+}
+
+ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val, double* C_val,
+                         hipStream_t s) {
+  if (!P) return PTAP_ERR_INPUT;
+  if (!P->sym_done) return PTAP_ERR_STATE;
+  if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!C_val && P->nnzC)) return PTAP_ERR_INPUT;
+  try {
+    numeric_impl(P, A_val, P_val, C_val, P->gtab, P->gval, s);
   } catch (...) {
-    const ptap_status st = caught_status();
-    return st;
+    return caught_status();
   }
   return PTAP_OK;
 }
@@ -1058,6 +1179,9 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->nblocks = P->opt.nblocks;
   out->cache_bytes = P->cache_bytes;
   out->block_size = P->bs;
+  out->staged_tiles = P->n_staged;
+  out->staged_lds_bytes = P->n_staged ? P->staged_L.total : 0;
+  out->table_slots = (int64_t)P->spill_slots;
   return PTAP_OK;
 }
 
@@ -1159,6 +1283,10 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       const NumericArgs& a = desc[k].a;
       if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
       const bool single = b->level_plans[l].size() == 1 || P->wide_a;
+      if (err == hipSuccess && P->n_staged)  // staged tiles: the plan's own launch
+        err = launch_staged(a, P->staged_tiles, P->n_staged, TileSet{P->tile_ptr, P->tile_rows, P->tile_slot},
+                            P->tile_fptr, P->tile_fine, P->halo_ptr, P->halo_rows, P->staged_L,
+                            P->opt.xcd_remap != 0, b->cap);
       for (const TileClass& c : P->tclasses) {
         if (err != hipSuccess) break;
         const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};

@@ -143,6 +143,90 @@ size_t owner_fast_lds_bytes(int TE, int nw);
 hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
                              const int* tile_fptr, const int* tile_fine, int TE, int nw,
                              bool xcd_remap, hipStream_t s);
+// Staged-tile owner kernel (staged.hip): a tile's halo rows of P are copied into LDS and R_I is
+// held in the positions of one of the tile's rows of C.  Tiles qualify when their fine rows have
+// at most kStagedMaxA entries in A(I,:) and kStagedMaxP in P(I,:), their rows of C at most
+// kStagedMaxRank entries, and the LDS layout of the launch fits the device.
+constexpr int kStagedWaves = 8;
+constexpr int kStagedMaxA = 28;
+constexpr int kStagedMaxP = 8;
+constexpr int kStagedMaxRank = 32;
+constexpr int kStagedMaxHalo = 4096;  // halo rows the symbolic pass can list per tile
+constexpr int kStagedMaxCols = 2048;  // distinct coarse columns it can count per tile
+constexpr int kStagedMaxRows = 1024;  // owned rows per tile (positions fit the 16-bit tables)
+constexpr int kStagedTileEntries = 1728;  // default tile size (entries of C) when staging
+
+struct StagedCaps {  // maxima over the tiles of one launch
+  int NR;  // owned rows of C
+  int TE;  // entries of those rows
+  int NH;  // halo rows
+  int SE;  // entries of P in the halo rows
+  int UL;  // distinct coarse columns among them
+};
+struct StagedLayout {  // dynamic LDS of one launch: capacities and byte offsets
+  int NR, TE, NH, SE, ULp, JHlog, UHlog;
+  int o_sval, o_tv, o_R, o_rec, o_jh, o_scol, o_tcl, o_trp, o_tcs, o_own, o_M, total;
+};
+
+inline int host_log2_ceil(long long v) {
+  int b = 0;
+  while ((1LL << b) < v) ++b;
+  return b;
+}
+
+// LDS bytes of a staged launch with these caps and nw wavefronts (and the layout, if L is given).
+inline size_t staged_layout(const StagedCaps& c, int nw, StagedLayout* L) {
+  StagedLayout l{};
+  l.NR = c.NR;
+  l.TE = c.TE;
+  l.NH = c.NH;
+  l.SE = c.SE;
+  l.ULp = (c.UL + 3) & ~3;
+  l.JHlog = host_log2_ceil(std::max(64, c.NH + c.NH / 2));
+  l.UHlog = host_log2_ceil(std::max(64, 2 * c.UL));
+  auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+  size_t o = 0;
+  l.o_sval = (int)o;
+  o = al(o + (size_t)c.SE * 8);
+  l.o_tv = (int)o;
+  o = al(o + (size_t)c.TE * 8);
+  l.o_R = (int)o;
+  // R: 16 rows per wavefront of kStagedMaxRank + 1 doubles; the set-up temporaries share it
+  // fold records (16 bytes; at most 2 per lane) follow R
+  const size_t rbytes = (size_t)nw * (WAVE / 4) * (kStagedMaxRank + 1) * 8;
+  const size_t recbytes = (size_t)nw * 2 * WAVE * 16;
+  const size_t tbytes = (((size_t)2 << l.UHlog) + 3 * (size_t)c.NH + 1 + (size_t)c.SE + (size_t)c.NR) * 4 +
+                        (size_t)c.TE * 2;
+  l.o_rec = (int)(o + rbytes);
+  o = al(o + std::max(rbytes + recbytes, tbytes));
+  l.o_jh = (int)o;
+  o = al(o + ((size_t)8 << l.JHlog));
+  l.o_scol = (int)o;
+  o = al(o + (size_t)c.SE * 2);
+  l.o_tcl = (int)o;
+  o = al(o + (size_t)c.TE * 2);
+  l.o_trp = (int)o;
+  o = al(o + ((size_t)c.NR + 1) * 4);
+  l.o_tcs = (int)o;
+  o = al(o + (size_t)c.NR * 4);
+  l.o_own = (int)o;
+  o = al(o + (size_t)l.ULp * 2);
+  l.o_M = (int)o;
+  o = al(o + (size_t)c.NR * l.ULp);
+  l.total = (int)o;
+  if (L) *L = l;
+  return o;
+}
+// Count pass (fill = false): stats[6t..6t+5] for every listed tile t (halo rows, their entries of
+// P, distinct coarse columns, longest row of A and of P over the fine rows, table overflow).
+// Fill pass: the sorted halo rows of the listed tiles into halo_rows at halo_ptr[t].
+hipError_t launch_tile_halo(const Patterns& p, const int* tiles, int ntiles, const int* tile_fptr,
+                            const int* tile_fine, bool fill, int* stats, const int* halo_ptr,
+                            int* halo_rows, hipStream_t s);
+hipError_t launch_staged(const NumericArgs& a, const int* tiles, int ntiles, const TileSet& ts,
+                         const int* tile_fptr, const int* tile_fine, const int* halo_ptr,
+                         const int* halo_rows, const StagedLayout& L, bool xcd_remap, hipStream_t s);
+
 // Batched owner fold: a device-side description of one plan (values included).
 struct OwnerBatchPlan {
   NumericArgs a;

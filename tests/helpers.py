@@ -32,11 +32,32 @@ def assert_close(got, ref, ref_abs, what="values", rel=REL, abs_frac=ABS_FRAC):
 
 
 def strict_report(got, ref):
-    """Count of entries beyond the plain 1e-12 relative criterion and the worst ratio."""
+    """Count of entries beyond the plain 1e-12 relative criterion and the worst relative error
+    (an entry whose reference is exactly 0 counts as infinitely far off unless it is 0 too)."""
     got = np.asarray(got); ref = np.asarray(ref)
     err = np.abs(got - ref)
     rel = np.where(ref != 0, err / np.where(ref != 0, np.abs(ref), 1.0), np.where(err > 0, np.inf, 0.0))
     return int((rel > REL).sum()), float(rel.max() if rel.size else 0.0)
+
+
+def parity_report(name, got, ref, ref_ld=None):
+    """One line on how a result compares with the oracle under the plain 1e-12 relative test,
+    beside the criterion the tests apply: entries beyond 1e-12 relative, the worst relative error,
+    the worst error as a fraction of |P|^T |A| |P| (the criterion's second bound), and the same
+    against the oracle's long-double sums when given.  Printed (run pytest with -s to see it) and
+    returned as a dict."""
+    got = np.asarray(got, dtype=np.float64)
+    n, worst = strict_report(got, ref.val)
+    frac = float((np.abs(got - ref.val) / np.where(ref.abs > 0, ref.abs, 1.0)).max()) if got.size else 0.0
+    out = {"entries": int(got.size), "beyond_1e-12": n, "max_rel": worst, "max_err_over_Cabs": frac}
+    if ref_ld is not None:
+        n2, w2 = strict_report(got, ref_ld.val)
+        n3, w3 = strict_report(ref.val, ref_ld.val)
+        out.update({"beyond_1e-12_vs_long_double": n2, "max_rel_vs_long_double": w2,
+                    "oracle_fp64_beyond_1e-12_vs_long_double": n3, "oracle_fp64_max_rel_vs_long_double": w3})
+    print(f"PARITY {name}: " + ", ".join(f"{k}={v:.3g}" if isinstance(v, float) else f"{k}={v}"
+                                         for k, v in out.items()))
+    return out
 
 
 def dense(M) -> np.ndarray:

@@ -37,6 +37,22 @@ def test_null_arguments_rejected_without_gpu():
     lib.ptap_plan_destroy(None)  # accepts NULL
 
 
+def test_counts_beyond_int32_rejected_without_gpu():
+    """nnz(A) or nnz(P) past int32 indexing is PTAP_ERR_TOO_LARGE, reported before any device
+    call (the pointers are never read)."""
+    fake = ctypes.c_void_p(0x1000)
+    L = lib.load_library()
+    for a_nnz, p_nnz in [(2**31, 10), (10, 2**31), (2**40, 2**40)]:
+        h = ctypes.c_void_p()
+        st = L.ptap_plan_create(ctypes.byref(h), 10, 4, fake, fake, a_nnz, fake, fake, p_nnz, None, None, None)
+        assert st == lib.PTAP_ERR_TOO_LARGE and not h.value, (a_nnz, p_nnz, st)
+        h = ctypes.c_void_p()
+        st = L.ptap_plan_create_bsr(ctypes.byref(h), 10, 4, 3, fake, fake, a_nnz, fake, fake, p_nnz,
+                                    None, None, None)
+        assert st == lib.PTAP_ERR_TOO_LARGE and not h.value, (a_nnz, p_nnz, st)
+    assert L.ptap_copy_pattern(None, None, None, None) == lib.PTAP_ERR_INPUT
+
+
 gpu = pytest.mark.gpu
 
 
