@@ -220,6 +220,21 @@ ptap_status ptap_numeric(ptap_plan* plan, const double* A_val, const double* P_v
                          hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory at all during the numeric call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the numeric phase of
+ * ptap_numeric with the same kernels and the same result, which neither allocates nor uses the
+ * plan's workspace for scratch.  The general kernels' device-memory hash tables (rows whose tables
+ * do not fit in LDS) live in a fixed array of the library instead: 2^20 slots (4-byte keys and
+ * 8-byte values, 12 MiB), one array per GPU, held from the first call on that GPU until the
+ * process ends, and cleared at the start of every call by fill kernels on the stream (no memset).
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other threads) race and must not be made.  Errors: as ptap_numeric, plus PTAP_ERR_TOO_LARGE when
+ * the plan's tables need more than 2^20 slots (ptap_numeric then still works).
+ */
+ptap_status ptap_numeric_noalloc(ptap_plan* plan, const double* A_val, const double* P_val,
+                                 double* C_val, hipStream_t stream);
+
+/*
  * Adjoint of the numeric phase.  Given dC = dL/dC on the pattern of C, writes
  *   dA = P dC P^T                 restricted to the pattern of A  (A_nnz values), and
  *   dP = A P dC^T + A^T P dC      restricted to the pattern of P  (P_nnz values),

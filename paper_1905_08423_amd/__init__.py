@@ -77,6 +77,7 @@ _SIGNATURES = {
     "ptap_get_pattern": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "ptap_copy_pattern": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "ptap_numeric": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "ptap_numeric_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "ptap_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "ptap_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ptap_stats)]),
     "ptap_plan_destroy": (None, [_vp]),
@@ -190,6 +191,10 @@ def ptap_copy_pattern(plan, C_rowptr, C_col, stream=None):
 
 def ptap_numeric(plan, A_val, P_val, C_val, stream=None):
     return load_library().ptap_numeric(plan, _ptr(A_val), _ptr(P_val), _ptr(C_val), _stream(stream))
+
+
+def ptap_numeric_noalloc(plan, A_val, P_val, C_val, stream=None):
+    return load_library().ptap_numeric_noalloc(plan, _ptr(A_val), _ptr(P_val), _ptr(C_val), _stream(stream))
 
 
 def ptap_backward(plan, A_val, P_val, dC_val, dA_val, dP_val, stream=None):

@@ -1140,6 +1140,32 @@ ptap_status ptap_numeric(ptap_plan* P, const double* A_val, const double* P_val,
   return PTAP_OK;
 }
 
+// The numeric phase with the general kernels' device-memory hash tables in caller-given memory of
+// `slots` keys and values: cleared here by fill kernels (the memory keeps whatever a previous
+// call left), then the same launches as ptap_numeric.  Used by ptap_numeric_noalloc.
+__attribute__((visibility("hidden"))) ptap_status numeric_with_scratch(
+    ptap_plan* P, const double* A_val, const double* P_val, double* C_val, int* keys, double* vals,
+    size_t slots, hipStream_t s) {
+  if (!P) return PTAP_ERR_INPUT;
+  if (!P->sym_done) return PTAP_ERR_STATE;
+  if ((!A_val && P->nnzA) || (!P_val && P->nnzP) || (!C_val && P->nnzC)) return PTAP_ERR_INPUT;
+  if (P->spill_slots > slots) return PTAP_ERR_TOO_LARGE;
+  try {
+    if (P->spill_slots) {
+      hipck(launch_fill_i32(keys, EMPTY, (long long)P->spill_slots, s));
+      hipck(launch_fill_f64(vals, 0.0, (long long)P->spill_slots, s));
+    }
+    numeric_impl(P, A_val, P_val, C_val, P->spill_slots ? keys : nullptr, P->spill_slots ? vals : nullptr, s);
+  } catch (...) {
+    return caught_status();
+  }
+  return PTAP_OK;
+}
+
+__attribute__((visibility("hidden"))) size_t plan_scratch_slots(const ptap_plan* P) {
+  return P ? P->spill_slots : 0;
+}
+
 ptap_status ptap_backward(ptap_plan* P, const double* A_val, const double* P_val,
                           const double* dC_val, double* dA_val, double* dP_val, hipStream_t s) {
   if (!P) return PTAP_ERR_INPUT;
