@@ -143,7 +143,8 @@ typedef struct ptap_stats {
   int64_t staged_lds_bytes;    /* LDS bytes per workgroup of that kernel's launch (0: none) */
   int64_t table_slots;         /* device-memory hash-table slots the general kernels use (rows
                                   whose tables do not fit in LDS); 0 when every table is in LDS */
-  int64_t reserved[3];
+  int64_t tile_entries;        /* owner fold: entries of C a tile holds at most (0: no tiles) */
+  int64_t reserved[2];
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;

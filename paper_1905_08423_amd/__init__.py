@@ -57,7 +57,8 @@ class ptap_stats(ctypes.Structure):
                 ("algo", ctypes.c_int32), ("nblocks", ctypes.c_int32),
                 ("cache_bytes", ctypes.c_int64), ("block_size", ctypes.c_int64),
                 ("staged_tiles", ctypes.c_int64), ("staged_lds_bytes", ctypes.c_int64),
-                ("table_slots", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("table_slots", ctypes.c_int64), ("tile_entries", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

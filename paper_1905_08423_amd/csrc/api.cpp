@@ -1208,6 +1208,7 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->staged_tiles = P->n_staged;
   out->staged_lds_bytes = P->n_staged ? P->staged_L.total : 0;
   out->table_slots = (int64_t)P->spill_slots;
+  out->tile_entries = P->ntiles ? P->TE : 0;
   return PTAP_OK;
 }
 

@@ -8,8 +8,48 @@
 #include <thread>
 #include <vector>
 
+#if defined(__HIPCC__)
+#define PTAP_HD __host__ __device__
+#else
+#define PTAP_HD
+#endif
+
 namespace ptapk {
 namespace host {
+
+// LDS layout of the general owner kernel (one workgroup of `waves` wavefronts): the tile's values
+// (TE doubles) and columns (TE ints), its row offsets (1025 ints), one wavefront scratch of
+// `ws_bytes` bytes per wavefront (it holds doubles), then, for tables in LDS, `cap` doubles and
+// `cap` ints per wavefront.  Every region starts on a 16-byte boundary: with the regions packed
+// back to back, an odd TE left the doubles after the tile at addresses 4 mod 8, which FP64 LDS
+// accesses do not support.  A null tile (tile in device memory) takes no room.
+struct OwnerLayout {
+  size_t tv, tc, trp, ws, vals, keys, total;
+};
+PTAP_HD inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+PTAP_HD inline OwnerLayout owner_general_layout(long long TE, long long cap, int waves, size_t ws_bytes,
+                                                bool tile_in_lds, bool tables_in_lds) {
+  OwnerLayout l{};
+  size_t o = 0;
+  if (tile_in_lds) {
+    l.tv = o;
+    o = align16(o + (size_t)TE * 8);
+    l.tc = o;
+    o = align16(o + (size_t)TE * 4);
+    l.trp = o;
+    o = align16(o + (size_t)1025 * 4);
+  }
+  l.ws = o;
+  o = align16(o + (size_t)waves * ws_bytes);
+  if (tables_in_lds) {
+    l.vals = o;
+    o = align16(o + (size_t)waves * (size_t)cap * 8);
+    l.keys = o;
+    o = align16(o + (size_t)waves * (size_t)cap * 4);
+  }
+  l.total = o;
+  return l;
+}
 
 inline int next_pow2(long long v) {
   long long c = 1;

@@ -2,6 +2,7 @@
 // pattern of C, owner tiles), the numeric all-at-once / merged folds (atomic and owner), the
 // two-step comparison and the adjoint.
 #include "device.hpp"
+#include "host_logic.hpp"
 #include "internal.hpp"
 
 namespace ptapk {
@@ -750,7 +751,8 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
   const int tp = ts.ptr[tile], nr = ts.ptr[tile + 1] - tp;
   const Patterns& p = a.p;
 
-  unsigned char* sp = smem;
+  const host::OwnerLayout lay =
+      host::owner_general_layout(TE, cap, kWavesPerBlock, sizeof(WaveScratch), !TG, !HG);
   double* tv;
   const int* tc;
   int* trp = nullptr;
@@ -763,17 +765,13 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
     tc = a.C_col + c0;
     tg_len = a.C_rowptr[row + 1] - c0;
   } else {
-    tv = reinterpret_cast<double*>(sp);
-    sp += (size_t)TE * sizeof(double);
-    int* tcw = reinterpret_cast<int*>(sp);
-    sp += (size_t)TE * sizeof(int);
-    trp = reinterpret_cast<int*>(sp);
-    sp += (((size_t)kTileRows + 1) * sizeof(int) + 15) / 16 * 16;
+    tv = reinterpret_cast<double*>(smem + lay.tv);
+    int* tcw = reinterpret_cast<int*>(smem + lay.tc);
+    trp = reinterpret_cast<int*>(smem + lay.trp);
     tile_load(ts.rows, tp, nr, a.C_rowptr, a.C_col, trp, tcw, tv);
     tc = tcw;
   }
-  WaveScratch* ws = reinterpret_cast<WaveScratch*>(sp) + wid;
-  sp += kWavesPerBlock * sizeof(WaveScratch);
+  WaveScratch* ws = reinterpret_cast<WaveScratch*>(smem + lay.ws) + wid;
   int* keys;
   double* vals;
   if (HG) {
@@ -781,9 +779,8 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
     keys = gtab + (size_t)gw * cap;
     vals = gval + (size_t)gw * cap;
   } else {
-    vals = reinterpret_cast<double*>(sp) + (size_t)wid * cap;
-    sp += (size_t)kWavesPerBlock * cap * sizeof(double);
-    keys = reinterpret_cast<int*>(sp) + (size_t)wid * cap;
+    vals = reinterpret_cast<double*>(smem + lay.vals) + (size_t)wid * cap;
+    keys = reinterpret_cast<int*>(smem + lay.keys) + (size_t)wid * cap;
   }
   const unsigned mask = (unsigned)cap - 1;
   const int shift = 32 - log2_pow2(cap);
@@ -852,11 +849,8 @@ __global__ __launch_bounds__(kThreads) void k_owner_numeric(NumericArgs a,
 }
 
 size_t owner_general_lds_bytes(int TE, int cap, bool hash_global, bool tile_global) {
-  size_t lds = kWavesPerBlock * sizeof(WaveScratch);
-  if (!tile_global)
-    lds += (size_t)TE * (sizeof(double) + sizeof(int)) + (((size_t)kTileRows + 1) * sizeof(int) + 15) / 16 * 16;
-  if (!hash_global) lds += (size_t)kWavesPerBlock * cap * (sizeof(double) + sizeof(int));
-  return lds;
+  return host::owner_general_layout(TE, cap, kWavesPerBlock, sizeof(WaveScratch), !tile_global, !hash_global)
+      .total;
 }
 
 hipError_t launch_owner_numeric(const NumericArgs& a, const TileClass& tc, const TileSet& ts,

@@ -77,7 +77,46 @@ static void check_tiles(const char* name, int m, const std::vector<int>& ptr,
   std::printf("ok tiles %s (%d rows, %d ranges, %d tiles)\n", name, m, parts, T);
 }
 
+
+// LDS layout of the general owner kernel: every region aligned to 16 bytes and inside the total,
+// regions in order without overlap, for every tile size up to 8192 entries and the table
+// capacities the kernel takes.  The layout the kernel used before packed the regions back to back
+// (tile values, columns, 1025 row offsets rounded to 16 bytes, then the wavefront scratch that
+// holds doubles): for an odd tile size that put the doubles at addresses 4 mod 8.
+static void check_owner_layout() {
+  const size_t ws_bytes = 1024;  // WaveScratch: 64 ints, 64 ints, 64 doubles
+  for (long long TE = 1; TE <= 8192; ++TE)
+    for (long long cap : {64LL, 128LL, 256LL, 512LL, 1024LL})
+      for (int waves : {4, 8})
+        for (int tile = 0; tile < 2; ++tile)
+          for (int tab = 0; tab < 2; ++tab) {
+            const OwnerLayout l = owner_general_layout(TE, cap, waves, ws_bytes, tile, tab);
+            size_t end = 0;
+            auto region = [&](size_t off, size_t bytes, const char* what) {
+              if (off % 16 != 0) fail(what, TE, (long long)off);
+              if (off < end) fail("regions overlap", TE, (long long)off);
+              end = off + bytes;
+              if (end > l.total) fail("region past the total", TE, (long long)end);
+            };
+            if (tile) {
+              region(l.tv, (size_t)TE * 8, "tile values misaligned");
+              region(l.tc, (size_t)TE * 4, "tile columns misaligned");
+              region(l.trp, 1025 * 4, "row offsets misaligned");
+            }
+            region(l.ws, (size_t)waves * ws_bytes, "wavefront scratch misaligned");
+            if (tab) {
+              region(l.vals, (size_t)waves * (size_t)cap * 8, "table values misaligned");
+              region(l.keys, (size_t)waves * (size_t)cap * 4, "table keys misaligned");
+            }
+          }
+  // the packed layout: scratch at 12 TE + 4112 bytes, 4 mod 8 for every odd TE
+  for (long long TE = 1; TE < 5000; TE += 2)
+    if ((12 * TE + 4112) % 8 != 4) fail("packed layout arithmetic", TE, 0);
+  std::printf("ok owner layout aligned\n");
+}
+
 int main() {
+  check_owner_layout();
   // capacities: cap_log2 is the exponent of cap_for
   for (long long need = 1; need <= 300000; ++need)
     if ((1LL << cap_log2(need)) != cap_for(need)) fail("cap_log2", need);

@@ -58,11 +58,32 @@ def test_workloads_reduced(algo, fold, case):
     check_against_oracle(A, P, algo=algo, fold=fold)
 
 
-@pytest.mark.parametrize("algo,fold", [("merged", "owner"), ("merged", "atomic"), ("twostep", "auto")])
-def test_forced_spill(algo, fold):
-    """Hash tables capped at 64 slots: rows with more keys go to tables in device memory."""
-    A, P = _case("c3b_9")
-    check_against_oracle(A, P, algo=algo, fold=fold, hash_slots=64)
+@pytest.mark.parametrize("algo,fold", [("merged", "owner"), ("merged", "atomic"), ("twostep", "auto"),
+                                       ("allatonce", "owner")])
+@pytest.mark.parametrize("case", ["c3c_7", "random_long"])
+def test_forced_spill(algo, fold, case):
+    """Hash tables capped at 64 slots: rows of AP with more than 32 keys (up to 108 for the
+    4x4-block operator, 87 for the random one) go to tables in device memory; the plan reports
+    the slots it keeps there."""
+    if case == "random_long":
+        A = gen.random_csr(300, 300, 0.06, seed=31, empty_rows=0.05)
+        P = gen.random_csr(300, 90, 0.1, seed=32, empty_rows=0.05, zero_cols=3)
+    else:
+        A, P = _case(case)
+    st = check_against_oracle(A, P, algo=algo, fold=fold, hash_slots=64, nblocks=3 if algo == "allatonce" else 1)
+    assert st["table_slots"] > 0, st
+
+
+@pytest.mark.parametrize("te", [1593, 2105, 2361, 2729])
+def test_general_owner_kernel_odd_tile_size(te):
+    """The general owner kernel with an odd tile size: its LDS regions once sat back to back, so an
+    odd number of tile entries put the wavefront scratch and the tables' FP64 values at addresses
+    4 mod 8 (the failing runs had 1593 or 2729 entries).  The 4x4-block operator's rows of A hold
+    108 entries, so every scratch slot is used."""
+    A = gen.block_stencil27(12, 4, seed=2)
+    P = gen.block_smoothed_aggregation(A, 12, 4)
+    st = check_against_oracle(A, P, algo="merged", fold="owner", tile_entries=te)
+    assert st["tile_entries"] == te and te % 2 == 1
 
 
 @pytest.mark.parametrize("tile_entries", [16, 100, 700])
