@@ -60,7 +60,10 @@ typedef enum ptap_algo {
 
 /* How the outer product P(I,:) (x) R_I is added into C (all-at-once and merged only). */
 typedef enum ptap_fold {
-  PTAP_FOLD_AUTO = 0,   /* the owner fold (the faster one on MI355X) */
+  PTAP_FOLD_AUTO = 0,   /* per plan, the fold a cost model estimates faster from the symbolic
+                           phase's counts (rows formed by the owner fold against rows needed,
+                           products, fold terms), with constants measured on MI355X; the owner
+                           fold's tiles are built first and released if the atomic fold wins */
   PTAP_FOLD_ATOMIC = 1, /* fine-row sweep; device-wide FP64 atomic adds into C at the slot of
                            each (i, j), found through C's column list of row i */
   PTAP_FOLD_OWNER = 2   /* coarse-row ownership: a workgroup owns a tile of C rows (grown
@@ -144,7 +147,8 @@ typedef struct ptap_stats {
   int64_t table_slots;         /* device-memory hash-table slots the general kernels use (rows
                                   whose tables do not fit in LDS); 0 when every table is in LDS */
   int64_t tile_entries;        /* owner fold: entries of C a tile holds at most (0: no tiles) */
-  int64_t reserved[2];
+  double est_owner_ms;         /* PTAP_FOLD_AUTO: the fold cost model's estimate of the numeric */
+  double est_atomic_ms;        /* time with the owner and with the atomic fold (0 otherwise) */
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;
@@ -264,7 +268,8 @@ void ptap_plan_destroy(ptap_plan* plan);
  * every product with a smaller level (a coarse level's A is the previous level's C).  The
  * products of one level run together in one persistent launch that takes (plan, tile) work
  * items from per-XCD counters; a level holding a single plan uses that plan's own launch.
- * level may be NULL (all 0).  Only plans with the owner fold can be batched.
+ * level may be NULL (all 0).  Plans with the owner or the atomic fold can be batched (a plan
+ * with the atomic fold records its own launches into the graph); two-step plans are rejected.
  * The batch records its launches once into a HIP graph at the first ptap_batch_numeric call
  * and replays the graph afterwards; pointer arguments must therefore stay the same on every
  * call (their contents may change).

@@ -58,7 +58,7 @@ class ptap_stats(ctypes.Structure):
                 ("cache_bytes", ctypes.c_int64), ("block_size", ctypes.c_int64),
                 ("staged_tiles", ctypes.c_int64), ("staged_lds_bytes", ctypes.c_int64),
                 ("table_slots", ctypes.c_int64), ("tile_entries", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 2)]
+                ("est_owner_ms", ctypes.c_double), ("est_atomic_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

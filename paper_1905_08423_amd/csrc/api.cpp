@@ -261,7 +261,8 @@ struct ptap_plan {
   int bsr_n_lds = 0, bsr_n_glob = 0, bsr_cap = 64, bsr_ncmax = 0;
 
   int fold_used = PTAP_FOLD_OWNER;
-  int64_t rows_formed = 0, rows_needed = 0, fold_terms = 0;
+  int64_t rows_formed = 0, rows_needed = 0, fold_terms = 0, products = 0;
+  double est_owner_ms = 0.0, est_atomic_ms = 0.0;  // AUTO: the fold cost model's estimates
   int64_t pattern_bytes = 0;
 };
 
@@ -453,11 +454,10 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // --- |R_I| for every fine row (Alg. 1 / 2), tables sized by the product count w_I.
   int* r = t.get<int>(n);
   hipck(launch_fill_i32(r, 0, n, s));
+  int* w = t.get<int>(n);
   {
-    int* w = t.get<int>(n);
     hipck(launch_row_work(pat, w, s));  // min(w_I, m)
     std::vector<int> hw = to_host(w, n, s);
-    t.put(w);
     std::vector<RowClass> cls = make_classes_all(t, hw, P->lds_keys_max, s);
     size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
     int* gtab = gi ? t.get<int>(gi) : nullptr;
@@ -474,15 +474,17 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // longest rows, reduced on the device.
   int rmax_all = 0, pmax_all = 0;
   {
-    unsigned long long* st = t.get<unsigned long long>(4);
-    hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 8, s));
-    hipck(launch_row_stats(pat, r, st, s));
-    const std::vector<unsigned long long> h = to_host(st, 4, s);
+    unsigned long long* st = t.get<unsigned long long>(5);
+    hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
+    hipck(launch_row_stats(pat, r, w, st, s));
+    const std::vector<unsigned long long> h = to_host(st, 5, s);
     t.put(st);
+    t.put(w);
     P->rows_needed = (long long)h[0];
     P->fold_terms = (long long)h[1];
     rmax_all = (int)h[2];
     pmax_all = (int)h[3];
+    P->products = (long long)h[4];
   }
 
   // --- Two-step: the stored pattern of AP (rows sorted).
@@ -641,56 +643,10 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   } else {
     t.put(P->pt_pos);
     P->pt_pos = nullptr;
-    const bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
-    P->fold_used = atomic ? PTAP_FOLD_ATOMIC : PTAP_FOLD_OWNER;
-    if (atomic) {
-      // Single-pass forms: rows with |R_I| <= 32, at most 32 entries in P(I,:) and at most 32 in
-      // every row of C under them take the short-row kernel; the others the general one.
-      const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
-      RowMulArgs gf{};
-      gf.nX = gf.nY = n;
-      gf.nnzX = P->nnzA;
-      gf.nnzY = gf.nnzO = P->nnzP;
-      gf.nF = m;
-      gf.nnzF = P->nnzC;
-      const bool short_ok = !twopass && rowmul_short_fits(gf);
-      const std::vector<int>& hr = host_r();
-      const std::vector<int>& hP_rowptr = host_P_rowptr();
-      std::vector<int> hA_rowptr, hPc;
-      if (short_ok) {
-        hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
-        hPc = to_host(pat.P_col, (size_t)P->nnzP, s);
-      }
-      std::vector<int> rows, srows[2];
-      std::vector<long long> need;
-      for (int I = 0; I < n; ++I)
-        if (hP_rowptr[I + 1] > hP_rowptr[I] && hr[I] > 0) {
-          bool fits = short_ok && hr[I] <= kRowMulMaxLen &&
-                      hP_rowptr[I + 1] - hP_rowptr[I] <= kRowMulMaxLen;
-          for (int e = hP_rowptr[I]; fits && e < hP_rowptr[I + 1]; ++e)
-            fits = h_c_ptr[hPc[e] + 1] - h_c_ptr[hPc[e]] <= kRowMulMaxLen;
-          if (fits) {
-            srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
-          } else {
-            rows.push_back(I);
-            need.push_back(hr[I]);
-          }
-        }
-      P->arows = make_classes(t, rows, need, lmax, s);
-      for (int k = 0; k < 2; ++k) {
-        P->n_af_short[k] = (int)srows[k].size();
-        if (!srows[k].empty()) {
-          P->af_short[k] = t.get<int>(srows[k].size());
-          to_device(P->af_short[k], srows[k], s);
-        }
-      }
-      spill_need_ints = spill_ints(P->arows, 1);
-      spill_need_vals = spill_need_ints;
-      P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size()) * (twopass ? 2 : 1);
-      t.put(P->pt_ptr);
-      t.put(P->pt_row);
-      P->pt_ptr = P->pt_row = nullptr;
-    } else {
+    // AUTO: build the owner fold's tiles, then keep them or take the atomic fold after all,
+    // whichever the cost model of the two folds (host_logic.hpp fold_estimate) estimates faster.
+    bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
+    if (!atomic) {
       // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
@@ -918,6 +874,79 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         hipck(launch_pext(pat, P->nnzA, P->A_pext, s));
         P->cache_bytes = P->nnzA * (int64_t)sizeof(int);
       }
+      t.put(P->pt_ptr);
+      t.put(P->pt_row);
+      P->pt_ptr = P->pt_row = nullptr;
+      if (P->opt.fold == PTAP_FOLD_AUTO) {
+        const bool twopass_fold = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+        const host::FoldEstimate est = host::fold_estimate(P->rows_needed, P->rows_formed, P->products,
+                                                           P->fold_terms, twopass_fold);
+        P->est_owner_ms = est.owner_ms;
+        P->est_atomic_ms = est.atomic_ms;
+        if (est.atomic_ms < est.owner_ms) {
+          // release everything the owner fold built
+          for (TileClass& tc : P->tclasses) t.put(tc.tiles);
+          P->tclasses.clear();
+          for (int** q : {&P->tile_ptr, &P->tile_rows, &P->tile_slot, &P->tile_fptr, &P->tile_fine,
+                          &P->off_fptr, &P->off_fine, &P->staged_tiles, &P->halo_ptr, &P->halo_rows,
+                          &P->A_pext}) {
+            t.put(*q);
+            *q = nullptr;
+          }
+          P->host_fptr.clear();
+          P->ntiles = P->TE = P->n_staged = 0;
+          P->any_tile_global = false;
+          P->cache_bytes = 0;
+          spill_need_ints = spill_need_vals = 0;
+          atomic = true;
+        }
+      }
+    }
+    P->fold_used = atomic ? PTAP_FOLD_ATOMIC : PTAP_FOLD_OWNER;
+    if (atomic) {
+      // Single-pass forms: rows with |R_I| <= 32, at most 32 entries in P(I,:) and at most 32 in
+      // every row of C under them take the short-row kernel; the others the general one.
+      const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
+      RowMulArgs gf{};
+      gf.nX = gf.nY = n;
+      gf.nnzX = P->nnzA;
+      gf.nnzY = gf.nnzO = P->nnzP;
+      gf.nF = m;
+      gf.nnzF = P->nnzC;
+      const bool short_ok = !twopass && rowmul_short_fits(gf);
+      const std::vector<int>& hr = host_r();
+      const std::vector<int>& hP_rowptr = host_P_rowptr();
+      std::vector<int> hA_rowptr, hPc;
+      if (short_ok) {
+        hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
+        hPc = to_host(pat.P_col, (size_t)P->nnzP, s);
+      }
+      std::vector<int> rows, srows[2];
+      std::vector<long long> need;
+      for (int I = 0; I < n; ++I)
+        if (hP_rowptr[I + 1] > hP_rowptr[I] && hr[I] > 0) {
+          bool fits = short_ok && hr[I] <= kRowMulMaxLen &&
+                      hP_rowptr[I + 1] - hP_rowptr[I] <= kRowMulMaxLen;
+          for (int e = hP_rowptr[I]; fits && e < hP_rowptr[I + 1]; ++e)
+            fits = h_c_ptr[hPc[e] + 1] - h_c_ptr[hPc[e]] <= kRowMulMaxLen;
+          if (fits) {
+            srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
+          } else {
+            rows.push_back(I);
+            need.push_back(hr[I]);
+          }
+        }
+      P->arows = make_classes(t, rows, need, lmax, s);
+      for (int k = 0; k < 2; ++k) {
+        P->n_af_short[k] = (int)srows[k].size();
+        if (!srows[k].empty()) {
+          P->af_short[k] = t.get<int>(srows[k].size());
+          to_device(P->af_short[k], srows[k], s);
+        }
+      }
+      spill_need_ints = spill_ints(P->arows, 1);
+      spill_need_vals = spill_need_ints;
+      P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size()) * (twopass ? 2 : 1);
       t.put(P->pt_ptr);
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
@@ -1209,6 +1238,8 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->staged_lds_bytes = P->n_staged ? P->staged_L.total : 0;
   out->table_slots = (int64_t)P->spill_slots;
   out->tile_entries = P->ntiles ? P->TE : 0;
+  out->est_owner_ms = P->est_owner_ms;
+  out->est_atomic_ms = P->est_atomic_ms;
   return PTAP_OK;
 }
 
@@ -1228,8 +1259,7 @@ ptap_status ptap_batch_create(ptap_batch** out, ptap_plan* const* plans, const i
     if (!plans[k]) return PTAP_ERR_INPUT;
     if (plans[k]->bs > 1) return PTAP_ERR_UNSUPPORTED;
     if (!plans[k]->sym_done) return PTAP_ERR_STATE;
-    if (plans[k]->opt.algo == PTAP_TWOSTEP || plans[k]->fold_used != PTAP_FOLD_OWNER)
-      return PTAP_ERR_UNSUPPORTED;
+    if (plans[k]->opt.algo == PTAP_TWOSTEP) return PTAP_ERR_UNSUPPORTED;
   }
   ptap_batch* b = new (std::nothrow) ptap_batch();
   if (!b) return PTAP_ERR_OOM;
@@ -1310,6 +1340,16 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       const NumericArgs& a = desc[k].a;
       if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
       const bool single = b->level_plans[l].size() == 1 || P->wide_a;
+      if (P->fold_used == PTAP_FOLD_ATOMIC) {  // the atomic fold: the plan's own launches
+        if (err == hipSuccess) {
+          try {
+            numeric_impl(P, b->A_vals[k], b->P_vals[k], b->C_vals[k], P->gtab, P->gval, b->cap);
+          } catch (...) {
+            err = hipErrorUnknown;
+          }
+        }
+        continue;
+      }
       if (err == hipSuccess && P->n_staged)  // staged tiles: the plan's own launch
         err = launch_staged(a, P->staged_tiles, P->n_staged, TileSet{P->tile_ptr, P->tile_rows, P->tile_slot},
                             P->tile_fptr, P->tile_fine, P->halo_ptr, P->halo_rows, P->staged_L,

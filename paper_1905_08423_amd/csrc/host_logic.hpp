@@ -51,6 +51,34 @@ PTAP_HD inline OwnerLayout owner_general_layout(long long TE, long long cap, int
   return l;
 }
 
+// Choice of the fold for PTAP_FOLD_AUTO.  Which of the two ways of adding P(I,:) (x) R_I into C
+// is cheaper depends on the problem (Section 3 leaves the choice between the loops of Alg. 8 and
+// Alg. 10 open): the owner fold forms some rows R_I more than once (a fine row whose entries of P
+// fall in several tiles is formed in each) but adds in on-chip memory, the atomic fold forms each
+// row once and adds every term with a device-wide FP64 atomic.  The estimates are linear in the
+// symbolic phase's counts, with constants fitted (non-negative least squares on relative error)
+// to the measured numeric times of both folds on one MI355X over seven workloads: 27-point
+// lognormal operators at 128^3 and 64^3 and a 7-point one at 128^3 with trilinear P, smoothed
+// aggregation with one and two Jacobi steps at 96^3 and two at 48^3, and a 4x4-block operator.
+//   owner  = 0.161 ms per million rows formed + 0.00334 ms per million products formed
+//            (products of the needed rows times rows formed / rows needed)
+//   atomic = 0.100 ms per million rows formed + 0.0206 ms per million fold terms
+// (the atomic fold forms each needed row once per pass).  The fit picks the faster fold on all
+// seven; the terms it drops (the owner fold's own adds, the atomic fold's products) came out at
+// zero weight.
+struct FoldEstimate {
+  double owner_ms, atomic_ms;
+};
+inline FoldEstimate fold_estimate(long long rows_needed, long long rows_formed_owner, long long products,
+                                  long long fold_terms, bool two_passes) {
+  FoldEstimate e{0.0, 0.0};
+  if (rows_needed <= 0) return e;
+  const double r = (double)rows_formed_owner / (double)rows_needed;
+  e.owner_ms = 0.161e-6 * (double)rows_formed_owner + 0.00334e-6 * (double)products * r;
+  e.atomic_ms = 0.100e-6 * (double)rows_needed * (two_passes ? 2.0 : 1.0) + 0.0206e-6 * (double)fold_terms;
+  return e;
+}
+
 inline int next_pow2(long long v) {
   long long c = 1;
   while (c < v) c <<= 1;

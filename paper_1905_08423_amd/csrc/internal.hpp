@@ -63,8 +63,10 @@ hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_
 hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
                                  int* t_row, int* t_pos, hipStream_t s);
 hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s);  // min(w_I, m)
-// needed rows, fold terms, max |R_I|, max(nnz(P(I,:)), nnz(A(I,:))); out zeroed by the caller
-hipError_t launch_row_stats(const Patterns& p, const int* r, unsigned long long* out, hipStream_t s);
+// out[0..4]: needed rows, fold terms, max |R_I|, max(nnz(P(I,:)), nnz(A(I,:))), products
+// A(I,J) P(J,j) of the needed rows (the sum of w over them); out zeroed by the caller
+hipError_t launch_row_stats(const Patterns& p, const int* r, const int* w, unsigned long long* out,
+                            hipStream_t s);
 hipError_t launch_ap_row_count(const Patterns& p, const RowClass& rc, int* r_out, int* gtab,
                                hipStream_t s);
 hipError_t launch_ap_row_fill(const Patterns& p, const RowClass& rc, const int* AP_rowptr,

@@ -175,11 +175,12 @@ hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s) {
 // both non-empty (the rows the fold needs), out[1] = sum_I nnz(P(I,:)) |R_I| (fold terms),
 // out[2] = max_I |R_I|, out[3] = max_I max(nnz(P(I,:)), nnz(A(I,:))).  out holds zeros on entry.
 // Launched with 256 threads per block.
-__global__ void k_row_stats(Patterns p, const int* __restrict__ r, unsigned long long* out) {
-  __shared__ unsigned long long sh[4][256];
+__global__ void k_row_stats(Patterns p, const int* __restrict__ r, const int* __restrict__ w,
+                            unsigned long long* out) {
+  __shared__ unsigned long long sh[5][256];
   const int t = threadIdx.x;
   const int I = blockIdx.x * blockDim.x + t;
-  unsigned long long v[4] = {0, 0, 0, 0};
+  unsigned long long v[5] = {0, 0, 0, 0, 0};
   if (I < p.n) {
     const int lp = p.P_rowptr[I + 1] - p.P_rowptr[I];
     const int la = p.A_rowptr[I + 1] - p.A_rowptr[I];
@@ -187,12 +188,13 @@ __global__ void k_row_stats(Patterns p, const int* __restrict__ r, unsigned long
     if (lp > 0 && rI > 0) {
       v[0] = 1;
       v[1] = (unsigned long long)lp * (unsigned long long)rI;
+      v[4] = (unsigned long long)w[I];
     }
     v[2] = rI > 0 ? (unsigned long long)rI : 0;
     const int l = lp > la ? lp : la;
     v[3] = l > 0 ? (unsigned long long)l : 0;
   }
-  for (int q = 0; q < 4; ++q) sh[q][t] = v[q];
+  for (int q = 0; q < 5; ++q) sh[q][t] = v[q];
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if (t < h) {
@@ -200,10 +202,12 @@ __global__ void k_row_stats(Patterns p, const int* __restrict__ r, unsigned long
       sh[1][t] += sh[1][t + h];
       sh[2][t] = sh[2][t] > sh[2][t + h] ? sh[2][t] : sh[2][t + h];
       sh[3][t] = sh[3][t] > sh[3][t + h] ? sh[3][t] : sh[3][t + h];
+      sh[4][t] += sh[4][t + h];
     }
     __syncthreads();
   }
   if (t == 0) {
+    atomicAdd(out + 4, sh[4][0]);
     atomicAdd(out, sh[0][0]);
     atomicAdd(out + 1, sh[1][0]);
     atomicMax(out + 2, sh[2][0]);
@@ -211,9 +215,10 @@ __global__ void k_row_stats(Patterns p, const int* __restrict__ r, unsigned long
   }
 }
 
-hipError_t launch_row_stats(const Patterns& p, const int* r, unsigned long long* out, hipStream_t s) {
+hipError_t launch_row_stats(const Patterns& p, const int* r, const int* w, unsigned long long* out,
+                            hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_stats, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, r, out);
+  hipLaunchKernelGGL(k_row_stats, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, r, w, out);
   return hipGetLastError();
 }
 

@@ -115,7 +115,33 @@ static void check_owner_layout() {
   std::printf("ok owner layout aligned\n");
 }
 
+
+// The fold cost model: the measured cases of its fit each pick the fold that was faster.
+static void check_fold_estimate() {
+  struct Case {
+    const char* name;
+    long long needed, formed, products, fold;
+    bool atomic_faster;
+  } cases[] = {
+      {"27pt 128^3 trilinear", 2097152, 2891040, 186169411, 86938307, false},
+      {"SA one step 96^3", 884736, 1475244, 105154048, 40707584, false},
+      {"SA two steps 96^3", 884736, 3173617, 284890312, 274625000, false},
+      {"27pt 64^3 trilinear", 262144, 388764, 22665187, 10503459, false},
+      {"7pt 128^3 trilinear", 2097152, 2891040, 48556211, 69839855, false},
+      {"SA two steps 48^3", 110592, 604294, 33386248, 30959144, true},
+      {"4x4 blocks 40^3", 256000, 838104, 474552000, 187149248, true},
+  };
+  for (const Case& c : cases) {
+    const FoldEstimate e = fold_estimate(c.needed, c.formed, c.products, c.fold, false);
+    if ((e.atomic_ms < e.owner_ms) != c.atomic_faster) fail(c.name, (long long)(e.owner_ms * 1e3), (long long)(e.atomic_ms * 1e3));
+  }
+  const FoldEstimate z = fold_estimate(0, 0, 0, 0, false);
+  if (z.owner_ms != 0.0 || z.atomic_ms != 0.0) fail("empty problem", 0, 0);
+  std::printf("ok fold estimate\n");
+}
+
 int main() {
+  check_fold_estimate();
   check_owner_layout();
   // capacities: cap_log2 is the exponent of cap_for
   for (long long need = 1; need <= 300000; ++need)

@@ -222,3 +222,24 @@ def test_hierarchy_256_six_levels_bit_exact():
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_auto_fold_choice():
+    """PTAP_FOLD_AUTO takes the fold the cost model estimates faster (the owner fold where few
+    rows of AP are formed twice, the atomic fold where many are or the rows are long), and the
+    product is the same: the 128^3 and 96^3 two-step-smoothed-aggregation workloads keep the owner
+    fold, the 48^3 two-step smoothed aggregation and the 4x4-block operator at 40^3 nodes take the
+    atomic fold; each against the oracle."""
+    A2 = gen.stencil27(48, seed=2, eps_z=0.01)
+    cases = [("c2", *gen.galerkin_workload("c2")[:2], lib.PTAP_FOLD_OWNER),
+             ("c3b", *gen.galerkin_workload("c3b")[:2], lib.PTAP_FOLD_OWNER),
+             ("sa2_48", A2, gen.smoothed_aggregation(A2, 48, 48, 48, steps=2), lib.PTAP_FOLD_ATOMIC)]
+    Ab = gen.block_stencil27(40, 4, seed=2)
+    cases.append(("block_40", Ab, gen.block_smoothed_aggregation(Ab, 40, 4), lib.PTAP_FOLD_ATOMIC))
+    for name, A, P, want in cases:
+        g = GpuProblem(A, P)
+        st = _check_full(g, _oracle(A, P), name=f"{name} auto fold", algo="merged", fold="auto")
+        assert st["fold_used"] == want, (name, st["est_owner_ms"], st["est_atomic_ms"])
+        assert st["est_owner_ms"] > 0 and st["est_atomic_ms"] > 0
+        print(f"PARITY {name}: auto fold {'atomic' if want == lib.PTAP_FOLD_ATOMIC else 'owner'}, "
+              f"estimates owner {st['est_owner_ms']:.3f} ms, atomic {st['est_atomic_ms']:.3f} ms")
