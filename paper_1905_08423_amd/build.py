@@ -21,7 +21,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-result"]
 
-SOURCES = ["kernels.hip", "owner.hip", "staged.hip", "bsr.hip", "adjoint.hip", "rowmul.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "owner.hip", "staged.hip", "bsr.hip", "adjoint.hip", "rowmul.hip", "noalloc.hip", "symbolic.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <exception>
 #include <map>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <tuple>
@@ -163,19 +164,203 @@ std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
       t, rows.size(), [&](size_t k) { return rows[k]; }, [&](size_t k) { return need[k]; }, lds_max, s);
 }
 
-// Every row 0 .. need.size()-1, with the bound need[k].
-template <class T>
-std::vector<RowClass> make_classes_all(Tracker& t, const std::vector<T>& need, int lds_max, hipStream_t s) {
-  return make_classes_by(
-      t, need.size(), [](size_t k) { return (int)k; }, [&](size_t k) { return (long long)need[k]; },
-      lds_max, s);
-}
-
 size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
   size_t need = 0;
   for (auto& c : cls)
     if (c.global) need = std::max(need, (size_t)kSpillWaves * c.cap * per_slot_ints);
   return need;
+}
+
+// Page-locked host memory for the symbolic phase's copies of patterns and counters.  Pinning
+// costs more than the copies themselves, so buffers go back to a process-wide pool after use
+// and are kept until the process ends, except those above kPinnedKeepBytes, which are freed.
+// A buffer waits for its stream before it is reused, so copies still in flight on an error
+// path never meet the next user.
+constexpr size_t kPinnedKeepBytes = (size_t)256 << 20;
+std::mutex g_pinned_mu;
+std::vector<std::pair<void*, size_t>> g_pinned_free;
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  PinnedBuf(size_t want, hipStream_t stream) : s(stream) {
+    want = std::max<size_t>(want, 4096);
+    {
+      std::lock_guard<std::mutex> lk(g_pinned_mu);
+      size_t best = g_pinned_free.size();
+      for (size_t k = 0; k < g_pinned_free.size(); ++k)
+        if (g_pinned_free[k].second >= want && (best == g_pinned_free.size() || g_pinned_free[k].second < g_pinned_free[best].second))
+          best = k;
+      if (best < g_pinned_free.size()) {
+        p = g_pinned_free[best].first;
+        bytes = g_pinned_free[best].second;
+        g_pinned_free.erase(g_pinned_free.begin() + (long)best);
+        return;
+      }
+    }
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(PTAP_ERR_OOM);
+    }
+    bytes = want;
+  }
+  ~PinnedBuf() {
+    if (!p) return;
+    (void)hipStreamSynchronize(s);
+    if (bytes > kPinnedKeepBytes) {
+      (void)hipHostFree(p);
+      return;
+    }
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_free.emplace_back(p, bytes);
+  }
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Device-to-host copy into page-locked memory, then wait.
+template <class T>
+void read_back(T* host, const T* dev, size_t count, hipStream_t s) {
+  if (count) hipck(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, s));
+  hipck(hipStreamSynchronize(s));
+}
+
+// Host-to-device copies staged through one page-locked arena (no wait: the arena outlives the
+// copies, which finish before the symbolic phase returns).  Copies that do not fit the arena
+// go through to_device.
+struct Uploads {
+  PinnedBuf buf;
+  size_t used = 0;
+  Uploads(size_t bytes, hipStream_t s) : buf(bytes, s) {}
+  template <class T>
+  void put(T* dev, const std::vector<T>& v) {
+    const size_t b = v.size() * sizeof(T);
+    if (!b) return;
+    if (used + b > buf.bytes) {
+      to_device(dev, v, buf.s);
+      return;
+    }
+    unsigned char* h = buf.as<unsigned char>() + used;
+    memcpy(h, v.data(), b);
+    hipck(hipMemcpyAsync(dev, h, b, hipMemcpyHostToDevice, buf.s));
+    used = (used + b + 255) & ~(size_t)255;
+  }
+};
+
+// Runs side() on a thread of its own (here, if no thread can start) while main() runs here;
+// rethrows what either threw once both are done.
+template <class F, class G>
+void run_beside(F&& side, G&& main_part) {
+  std::exception_ptr err;
+  auto wrapped = [&] {
+    try {
+      side();
+    } catch (...) {
+      err = std::current_exception();
+    }
+  };
+  std::thread th;
+  bool started = false;
+  try {
+    th = std::thread(wrapped);
+    started = true;
+  } catch (...) {
+  }
+  if (!started) wrapped();
+  try {
+    main_part();
+  } catch (...) {
+    if (started) th.join();
+    throw;
+  }
+  if (started) th.join();
+  if (err) std::rethrow_exception(err);
+}
+
+// Device classes from per-item codes (launch_class_build): the group sizes, read back after one
+// wait, and the rows of all groups in one allocation (*sorted; null if no row is kept).  The
+// classes built from it point into that allocation, so they are released together.
+std::vector<int> classes_from_codes(Tracker& t, const int* code, const int* list, int count, int nbins,
+                                    int** sorted, hipStream_t s) {
+  *sorted = nullptr;
+  std::vector<int> hist(nbins, 0);
+  if (count <= 0) return hist;
+  int* srt = t.get<int>(count);
+  const size_t cells1 = class_scratch_ints(count, nbins);
+  int* scr = t.get<int>(cells1);
+  long long* ss = t.get<long long>(scan_scratch_count((long long)cells1 - 1));
+  int* dh = t.get<int>(nbins + 1);
+  hipck(launch_fill_i32(dh, 0, nbins + 1, s));
+  hipck(launch_class_build(code, list, count, nbins, scr, ss, dh + nbins, srt, dh, s));
+  PinnedBuf hb((nbins + 1) * sizeof(int), s);
+  read_back(hb.as<int>(), dh, (size_t)nbins + 1, s);
+  for (int b = 0; b < nbins; ++b) hist[b] = hb.as<int>()[b];
+  const bool overflow = hb.as<int>()[nbins] != 0;
+  t.put(scr);
+  t.put(ss);
+  t.put(dh);
+  if (overflow) fail(PTAP_ERR_TOO_LARGE);
+  long long kept = 0;
+  for (int b = 0; b < nbins; ++b) kept += hist[b];
+  if (kept == 0)
+    t.put(srt);
+  else
+    *sorted = srt;
+  return hist;
+}
+
+// Capacity classes from the groups 0..30 of a class build (group b: tables of 2^b slots).
+std::vector<RowClass> cap_classes(const std::vector<int>& hist, int* sorted, int lds_max) {
+  std::vector<RowClass> out;
+  long long off = 0;
+  for (int b = 0; b < (int)hist.size(); ++b) {
+    if (hist[b] && b < 31) {
+      RowClass rc;
+      rc.cap = 1 << b;
+      rc.global = rc.cap > lds_max;
+      rc.count = hist[b];
+      rc.rows = sorted + off;
+      out.push_back(rc);
+    }
+    off += hist[b];
+  }
+  return out;
+}
+
+// Start of group b of a class build.
+int* group_rows(const std::vector<int>& hist, int* sorted, int b) {
+  long long off = 0;
+  for (int q = 0; q < b; ++q) off += hist[q];
+  return hist[b] ? sorted + off : nullptr;
+}
+
+// Classes by hash capacity of the rows list[0..count) (list null: rows 0..count-1), with the
+// key bound need[row] (device).
+template <class T>
+std::vector<RowClass> make_classes_dev(Tracker& t, const T* need, const int* list, int count, int lds_max,
+                                       hipStream_t s) {
+  if (count <= 0) return {};
+  int* code = t.get<int>(count);
+  if constexpr (sizeof(T) == 8)
+    hipck(launch_cap_codes_i64(need, list, count, code, s));
+  else
+    hipck(launch_cap_codes_i32(need, list, count, code, s));
+  int* sorted = nullptr;
+  const std::vector<int> hist = classes_from_codes(t, code, list, count, 31, &sorted, s);
+  t.put(code);
+  return cap_classes(hist, sorted, lds_max);
+}
+
+// Release the rows of a set of classes built together (one allocation, or one per class).
+void put_classes(Tracker& t, std::vector<RowClass>& cls) {
+  for (auto& c : cls) t.put(c.rows);
+  cls.clear();
 }
 
 }  // namespace
@@ -406,15 +591,17 @@ ptap_status ptap_plan_create_bsr(ptap_plan** out, int32_t nb, int32_t mb, int32_
 
 static void validate_patterns(ptap_plan* P, hipStream_t s) {
   const Patterns& pat = P->pat;
-  int* err = P->mem.get<int>(1);
-  hipck(launch_fill_i32(err, 0, 1, s));
-  hipck(launch_validate(pat.A_rowptr, pat.A_col, pat.n, pat.n, P->nnzA, err, s));
-  hipck(launch_validate(pat.P_rowptr, pat.P_col, pat.n, pat.m, P->nnzP, err, s));
-  int h = 0;
-  hipck(hipMemcpyAsync(&h, err, sizeof(int), hipMemcpyDeviceToHost, s));
-  hipck(hipStreamSynchronize(s));
+  // [0] error bits, [1..4] two pairs of descent counts (A, P)
+  int* err = P->mem.get<int>(10);
+  hipck(launch_fill_i32(err, 0, 10, s));
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(err + 2);
+  hipck(launch_validate_pattern(pat.A_rowptr, pat.A_col, pat.n, pat.n, P->nnzA, err, cnt, s));
+  hipck(launch_validate_pattern(pat.P_rowptr, pat.P_col, pat.n, pat.m, P->nnzP, err, cnt + 2, s));
+  PinnedBuf hb(10 * sizeof(int), s);
+  read_back(hb.as<int>(), err, 10, s);
   P->mem.put(err);
-  if (h) fail(PTAP_ERR_INPUT);
+  const unsigned long long* hc = reinterpret_cast<const unsigned long long*>(hb.as<int>() + 2);
+  if (hb.as<int>()[0] || hc[0] != hc[1] || hc[2] != hc[3]) fail(PTAP_ERR_INPUT);
 }
 
 static void symbolic_impl(ptap_plan* P, hipStream_t s) {
@@ -426,23 +613,12 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // The patterns are caller-owned; with validation on they are checked again right before use,
   // so that arrays changed or released since plan creation are reported instead of read.
   if (P->opt.validate) validate_patterns(P, s);
-
-  // --- Column index lists of P (pattern transpose; integer only, no values).
-  std::vector<int> h_pt_ptr(m + 1, 0);
-  P->pt_ptr = t.get<int>(m + 1);
-  P->pt_row = t.get<int>(P->nnzP);
-  P->pt_pos = (two || blk) ? t.get<int>(P->nnzP) : nullptr;
-  {
-    int* cnt = t.get<int>(m + 1);
-    hipck(launch_fill_i32(cnt, 0, m + 1, s));
-    hipck(launch_count_cols(pat.P_col, P->nnzP, cnt, s));
-    std::vector<int> hc = to_host(cnt, m, s);
-    for (int i = 0; i < m; ++i) h_pt_ptr[i + 1] = h_pt_ptr[i] + hc[i];
-    to_device(P->pt_ptr, h_pt_ptr, s);
-    to_device(cnt, std::vector<int>(h_pt_ptr.begin(), h_pt_ptr.end() - 1), s);
-    hipck(launch_transpose_fill(pat.P_rowptr, pat.P_col, n, cnt, P->pt_row, P->pt_pos, s));
-    t.put(cnt);
-  }
+  // device counters read back together: [0] a scan total passed INT32_MAX, [1] rows of AP left
+  // to the class launches, [2] rows of C left to them; [4..5] a scan's 64-bit total (copied)
+  int* dflag = t.get<int>(8);
+  hipck(launch_fill_i32(dflag, 0, 8, s));
+  PinnedBuf small(4096, s);
+  int* hsm = small.as<int>();
   // Host copies of P's row pointers and of |R_I| (8 MB each at 128^3), made only by the branches
   // that walk them row by row.
   std::vector<int> hP_store, hr_store;
@@ -450,102 +626,167 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     if (hP_store.size() != (size_t)n + 1) hP_store = to_host(pat.P_rowptr, (size_t)n + 1, s);
     return hP_store;
   };
+  auto scan = [&](const int* in, long long count, int* out) {
+    long long* sc = t.get<long long>(scan_scratch_count(count));
+    hipck(launch_scan_i32(in, count, out, sc, dflag, s));
+    hipck(hipMemcpyAsync(dflag + 4, sc + (scan_scratch_count(count) - 1), sizeof(long long),
+                         hipMemcpyDeviceToDevice, s));
+    t.put(sc);
+  };
 
-  // --- |R_I| for every fine row (Alg. 1 / 2), tables sized by the product count w_I.
-  int* r = t.get<int>(n);
-  hipck(launch_fill_i32(r, 0, n, s));
-  int* w = t.get<int>(n);
+  // --- Column index lists of P (pattern transpose; integer only, no values).
+  P->pt_ptr = t.get<int>(m + 1);
+  P->pt_row = t.get<int>(P->nnzP);
+  P->pt_pos = (two || blk) ? t.get<int>(P->nnzP) : nullptr;
   {
-    hipck(launch_row_work(pat, w, s));  // min(w_I, m)
-    std::vector<int> hw = to_host(w, n, s);
-    std::vector<RowClass> cls = make_classes_all(t, hw, P->lds_keys_max, s);
-    size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
-    int* gtab = gi ? t.get<int>(gi) : nullptr;
-    for (auto& c : cls) hipck(launch_ap_row_count(pat, c, r, gtab, s));
-    for (auto& c : cls) t.put(c.rows);
-    t.put(gtab);
+    int* cnt = t.get<int>(m + 1);
+    hipck(launch_fill_i32(cnt, 0, m + 1, s));
+    hipck(launch_count_cols(pat.P_col, P->nnzP, cnt, s));
+    scan(cnt, m, P->pt_ptr);
+    if (m) hipck(hipMemcpyAsync(cnt, P->pt_ptr, (size_t)m * sizeof(int), hipMemcpyDeviceToDevice, s));
+    hipck(launch_transpose_fill(pat.P_rowptr, pat.P_col, n, cnt, P->pt_row, P->pt_pos, s));
+    t.put(cnt);
   }
+
+  // --- |R_I| and w_I for every fine row (Alg. 1 / 2) in one pass; rows whose products could
+  // outgrow its table go to launches by capacity class, sized by w_I.
+  int* r = t.get<int>(n);
+  int* w = t.get<int>(n);
+  int* c_cnt = nullptr;
+  unsigned char* c_flag = nullptr;
+  int* c_ovf = nullptr;
+  int n_c_ovf = 0;
+  int rmax_all = 0, pmax_all = 0;
+  {
+    int* ovf = t.get<int>(n);
+    hipck(launch_ap_count(pat, r, w, ovf, dflag + 1, s));
+    // --- Merged / all-at-once: count pass of C's pattern by the two-level union (needs no R_I)
+    if (!two) {
+      c_cnt = t.get<int>(m + 1);
+      c_flag = t.get<unsigned char>(m);
+      c_ovf = t.get<int>(m);
+      hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, false, c_cnt, c_flag, c_ovf, dflag + 2,
+                               nullptr, nullptr, s));
+    }
+    read_back(hsm, dflag, 4, s);
+    if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+    const int novf = hsm[1];
+    n_c_ovf = hsm[2];
+    if (novf > 0) {
+      std::vector<RowClass> cls = make_classes_dev(t, w, ovf, novf, P->lds_keys_max, s);
+      size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
+      int* gtab = gi ? t.get<int>(gi) : nullptr;
+      for (auto& c : cls) hipck(launch_ap_row_count(pat, c, r, gtab, s));
+      put_classes(t, cls);
+      t.put(gtab);
+    }
+    t.put(ovf);
+  }
+
   auto host_r = [&]() -> const std::vector<int>& {
     if (hr_store.size() != (size_t)n) hr_store = to_host(r, n, s);
     return hr_store;
   };
 
-  // --- Counters for the statistics (rows needed, fold terms sum_I nnz(P(I,:)) |R_I|) and the
-  // longest rows, reduced on the device.
-  int rmax_all = 0, pmax_all = 0;
+  // --- Counters for the statistics (rows needed, fold terms sum_I nnz(P(I,:)) |R_I|, longest
+  // rows, products), reduced on the device and read with nnz(C) below.
+  unsigned long long* st = t.get<unsigned long long>(5);
+  hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
+  hipck(launch_row_stats(pat, r, w, st, s));
+  t.put(w);
+
+  // --- Two-step: the stored pattern of AP (rows sorted).
+  if (two) {
+    P->AP_rowptr = t.get<int>(n + 1);
+    scan(r, n, P->AP_rowptr);
+    read_back(hsm, dflag, 6, s);
+    if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+    long long acc;
+    memcpy(&acc, hsm + 4, sizeof(acc));
+    P->nnzAP = acc;
+    P->AP_col = t.get<int>(acc);
+    P->ap_rows = make_classes_dev(t, r, nullptr, n, P->lds_keys_max, s);
+    size_t gi = spill_ints(P->ap_rows, 2);
+    int* gtab = gi ? t.get<int>(gi) : nullptr;
+    for (auto& c : P->ap_rows) hipck(launch_ap_row_fill(pat, c, P->AP_rowptr, P->AP_col, gtab, s));
+    t.put(gtab);
+    put_classes(t, P->ap_rows);
+  }
+
+  // --- Pattern of C by rows: counts, scan (the one read of nnz(C)), fill.
   {
-    unsigned long long* st = t.get<unsigned long long>(5);
-    hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
-    hipck(launch_row_stats(pat, r, w, st, s));
-    const std::vector<unsigned long long> h = to_host(st, 5, s);
+    if (two) {
+      // the union of the stored rows of AP under column i of P, tables sized by sum |R_I|
+      c_cnt = t.get<int>(m + 1);
+      long long* bound = t.get<long long>(m);
+      hipck(launch_c_bound(P->pt_ptr, P->pt_row, r, m, bound, s));
+      std::vector<RowClass> cls = make_classes_dev(t, bound, nullptr, m, P->lds_keys_max, s);
+      t.put(bound);
+      size_t gi = spill_ints(cls, 2);
+      int* gtab = gi ? t.get<int>(gi) : nullptr;
+      hipck(launch_fill_i32(c_cnt, 0, m, s));
+      for (auto& c : cls)
+        hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, false, c_cnt, nullptr,
+                            nullptr, gtab, s));
+      put_classes(t, cls);
+      t.put(gtab);
+    } else if (n_c_ovf > 0) {
+      // rows the two-level union left: tables sized by sum |R_I|
+      long long* bound = t.get<long long>(m);
+      hipck(launch_c_bound_list(P->pt_ptr, P->pt_row, r, c_ovf, n_c_ovf, m, bound, s));
+      std::vector<RowClass> cls = make_classes_dev(t, bound, c_ovf, n_c_ovf, P->lds_keys_max, s);
+      t.put(bound);
+      size_t gi = spill_ints(cls, 2);
+      int* gtab = gi ? t.get<int>(gi) : nullptr;
+      for (auto& c : cls)
+        hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, nullptr, nullptr, c, false, c_cnt, nullptr, nullptr,
+                            gtab, s));
+      put_classes(t, cls);
+      t.put(gtab);
+    }
+    P->C_rowptr = t.get<int>(m + 1);
+    scan(c_cnt, m, P->C_rowptr);
+    read_back(hsm, dflag, 6, s);
+    unsigned long long h[5];
+    read_back(reinterpret_cast<unsigned long long*>(hsm + 8), st, 5, s);
+    memcpy(h, hsm + 8, sizeof(h));
     t.put(st);
-    t.put(w);
+    if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+    long long acc;
+    memcpy(&acc, hsm + 4, sizeof(acc));
     P->rows_needed = (long long)h[0];
     P->fold_terms = (long long)h[1];
     rmax_all = (int)h[2];
     pmax_all = (int)h[3];
     P->products = (long long)h[4];
-  }
-
-  // --- Two-step: the stored pattern of AP (rows sorted).
-  std::vector<int> h_ap_ptr;
-  if (two) {
-    const std::vector<int>& hr = host_r();
-    h_ap_ptr.assign(n + 1, 0);
-    long long acc = 0;
-    for (int I = 0; I < n; ++I) {
-      acc += hr[I];
-      if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
-      h_ap_ptr[I + 1] = (int)acc;
-    }
-    P->nnzAP = acc;
-    P->AP_rowptr = t.get<int>(n + 1);
-    P->AP_col = t.get<int>(acc);
-    to_device(P->AP_rowptr, h_ap_ptr, s);
-    P->ap_rows = make_classes_all(t, hr, P->lds_keys_max, s);
-    size_t gi = spill_ints(P->ap_rows, 2);
-    int* gtab = gi ? t.get<int>(gi) : nullptr;
-    for (auto& c : P->ap_rows) hipck(launch_ap_row_fill(pat, c, P->AP_rowptr, P->AP_col, gtab, s));
-    t.put(gtab);
-  }
-
-  // --- Pattern of C by rows: counts, scan, fill.
-  std::vector<int> h_c_ptr(m + 1, 0);
-  {
-    long long* bound = t.get<long long>(m);
-    hipck(launch_c_bound(P->pt_ptr, P->pt_row, r, m, bound, s));
-    std::vector<long long> hb = to_host(bound, m, s);
-    t.put(bound);
-    std::vector<RowClass> cls = make_classes_all(t, hb, P->lds_keys_max, s);
-    size_t gi = spill_ints(cls, 2);
-    int* gtab = gi ? t.get<int>(gi) : nullptr;
-    int* cnt = t.get<int>(m);
-    hipck(launch_fill_i32(cnt, 0, m, s));
-    for (auto& c : cls)
-      hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, false, cnt,
-                          nullptr, nullptr, gtab, s));
-    for (auto& c : cls) t.put(c.rows);
-    t.put(gtab);
-    std::vector<int> hc = to_host(cnt, m, s);
-    t.put(cnt);
-    long long acc = 0;
-    for (int i = 0; i < m; ++i) {
-      acc += hc[i];
-      if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
-      h_c_ptr[i + 1] = (int)acc;
-    }
     P->nnzC = acc;
-    P->C_rowptr = t.get<int>(m + 1);
     P->C_col = t.get<int>(acc);
-    to_device(P->C_rowptr, h_c_ptr, s);
-    cls = make_classes_all(t, hc, P->lds_keys_max, s);
-    gi = spill_ints(cls, 2);
-    gtab = gi ? t.get<int>(gi) : nullptr;
-    for (auto& c : cls)
-      hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, true, nullptr,
-                          P->C_rowptr, P->C_col, gtab, s));
-    for (auto& c : cls) t.put(c.rows);
-    t.put(gtab);
+    if (two) {
+      std::vector<RowClass> cls = make_classes_dev(t, c_cnt, nullptr, m, P->lds_keys_max, s);
+      size_t gi = spill_ints(cls, 2);
+      int* gtab = gi ? t.get<int>(gi) : nullptr;
+      for (auto& c : cls)
+        hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, P->AP_rowptr, P->AP_col, c, true, nullptr, P->C_rowptr,
+                            P->C_col, gtab, s));
+      put_classes(t, cls);
+      t.put(gtab);
+    } else {
+      hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
+                               P->C_rowptr, P->C_col, s));
+      if (n_c_ovf > 0) {
+        std::vector<RowClass> cls = make_classes_dev(t, c_cnt, c_ovf, n_c_ovf, P->lds_keys_max, s);
+        size_t gi = spill_ints(cls, 2);
+        int* gtab = gi ? t.get<int>(gi) : nullptr;
+        for (auto& c : cls)
+          hipck(launch_c_rows(pat, P->pt_ptr, P->pt_row, nullptr, nullptr, c, true, nullptr, P->C_rowptr,
+                              P->C_col, gtab, s));
+        put_classes(t, cls);
+        t.put(gtab);
+      }
+    }
+    t.put(c_cnt);
+    t.put(c_flag);
+    t.put(c_ovf);
     P->pattern_bytes = (int64_t)(m + 1 + acc) * (int64_t)sizeof(int);
   }
 
@@ -557,6 +798,9 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     // fit the LDS target are summed in LDS; longer rows add into C with device atomics.
     P->fold_used = PTAP_FOLD_OWNER;
     P->rows_formed = P->nnzP;  // a fine block row is formed once per block of its row of P
+    PinnedBuf cb(((size_t)m + 1) * sizeof(int), s);
+    read_back(cb.as<int>(), P->C_rowptr, (size_t)m + 1, s);
+    const int* h_c_ptr = cb.as<int>();
     const size_t target = std::min<size_t>((size_t)P->lds_device, 65536);
     int ncmax = 0;
     std::vector<int> lrows, grows;
@@ -587,12 +831,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->fold_used = PTAP_FOLD_AUTO;
     P->AP_val = t.get<double>(P->nnzAP);
     P->PT_val = t.get<double>(P->nnzP);
-    // AP rows already classed by exact |R_I|; reclass for maps (value tables have another LDS
-    // limit).  Rows with at most 32 entries in AP(I,:) (in C(i,:) for the second product) take
-    // the short-row kernel when every array fits its byte range.
-    for (auto& c : P->ap_rows) t.put(c.rows);
-    const std::vector<int>& hr = host_r();
-    std::vector<int> hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
+    // Rows with at most 32 entries in AP(I,:) (in C(i,:) for the second product) take the
+    // short-row kernel when every array fits its byte range; the others go by capacity class.
     RowMulArgs g1{}, g2{};
     g1.nX = g1.nY = g2.nY = n;  // A and P have n rows, P^T has m
     g2.nX = m;
@@ -601,52 +841,38 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     g1.nnzO = g2.nnzY = P->nnzAP;
     g2.nnzO = P->nnzC;
     const bool short_ok = rowmul_short_fits(g1) && rowmul_short_fits(g2);
-    std::vector<int> rows, srows[2];
-    std::vector<long long> need;
-    for (int I = 0; I < n; ++I)
-      if (hr[I] > 0) {
-        if (short_ok && hr[I] <= kRowMulMaxLen) {
-          srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
-        } else {
-          rows.push_back(I);
-          need.push_back(hr[I]);
-        }
-      }
-    P->ap_rows = make_classes(t, rows, need, lmax, s);
-    std::vector<int> crow, scrow[2];
-    std::vector<long long> cneed;
-    for (int i = 0; i < m; ++i)
-      if (h_c_ptr[i + 1] > h_c_ptr[i]) {
-        if (short_ok && h_c_ptr[i + 1] - h_c_ptr[i] <= kRowMulMaxLen) {
-          scrow[h_pt_ptr[i + 1] - h_pt_ptr[i] > kHalfLanes].push_back(i);
-        } else {
-          crow.push_back(i);
-          cneed.push_back(h_c_ptr[i + 1] - h_c_ptr[i]);
-        }
-      }
-    P->ptc_rows = make_classes(t, crow, cneed, lmax, s);
+    int* code = t.get<int>(std::max(n, m));
+    hipck(launch_rowform_codes(0, n, r, pat.A_rowptr, nullptr, nullptr, nullptr, short_ok, code, s));
+    int* sa = nullptr;
+    const std::vector<int> ha = classes_from_codes(t, code, nullptr, n, kCodeShort1 + 1, &sa, s);
+    hipck(launch_rowform_codes(1, m, nullptr, P->pt_ptr, P->C_rowptr, nullptr, nullptr, short_ok, code, s));
+    int* sc = nullptr;
+    const std::vector<int> hc = classes_from_codes(t, code, nullptr, m, kCodeShort1 + 1, &sc, s);
+    t.put(code);
+    P->ap_rows = cap_classes(ha, sa, lmax);
+    P->ptc_rows = cap_classes(hc, sc, lmax);
+    long long kept = 0;
+    for (int v : ha) kept += v;
     for (int k = 0; k < 2; ++k) {
-      P->n_ap_short[k] = (int)srows[k].size();
-      if (!srows[k].empty()) {
-        P->ap_short[k] = t.get<int>(srows[k].size());
-        to_device(P->ap_short[k], srows[k], s);
-      }
-      P->n_ptc_short[k] = (int)scrow[k].size();
-      if (!scrow[k].empty()) {
-        P->ptc_short[k] = t.get<int>(scrow[k].size());
-        to_device(P->ptc_short[k], scrow[k], s);
-      }
+      P->n_ap_short[k] = ha[kCodeShort0 + k];
+      P->ap_short[k] = group_rows(ha, sa, kCodeShort0 + k);
+      P->n_ptc_short[k] = hc[kCodeShort0 + k];
+      P->ptc_short[k] = group_rows(hc, sc, kCodeShort0 + k);
     }
     spill_need_ints = std::max(spill_ints(P->ap_rows, 1), spill_ints(P->ptc_rows, 1));
     spill_need_vals = spill_need_ints;
-    P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size());
+    P->rows_formed = kept;
   } else {
-    t.put(P->pt_pos);
-    P->pt_pos = nullptr;
     // AUTO: build the owner fold's tiles, then keep them or take the atomic fold after all,
     // whichever the cost model of the two folds (host_logic.hpp fold_estimate) estimates faster.
     bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
     if (!atomic) {
+      // C's pattern on the host for growing the tiles (one copy into page-locked memory)
+      PinnedBuf cbuf(((size_t)m + 1 + (size_t)P->nnzC) * sizeof(int), s);
+      int* h_c_ptr = cbuf.as<int>();
+      int* h_c_col = h_c_ptr + m + 1;
+      if (P->nnzC) hipck(hipMemcpyAsync(h_c_col, P->C_col, (size_t)P->nnzC * sizeof(int), hipMemcpyDeviceToHost, s));
+      read_back(h_c_ptr, P->C_rowptr, (size_t)m + 1, s);
       // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
@@ -693,42 +919,41 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         }
       }
       P->TE = TE;
-      std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
       std::vector<int> tptr, trows;
       std::vector<char> tglob;
-      grow_tiles(m, h_c_ptr.data(), h_c_col.data(), TE, TR, tptr, trows, tglob);
-      P->hash_mul = choose_hash_mul(m, h_c_ptr, h_c_col);
+      // the hash multiplier is chosen on a thread of its own while the tiles grow
+      run_beside([&] { P->hash_mul = choose_hash_mul(m, h_c_ptr, h_c_col); },
+                 [&] { grow_tiles(m, h_c_ptr, h_c_col, TE, TR, tptr, trows, tglob); });
       const int T = (int)tglob.size();
       if (T >= (1 << (31 - kTileRowBits))) fail(PTAP_ERR_TOO_LARGE);
-      std::vector<int> slot(m, -1);
-      for (int k = 0; k < T; ++k)
-        for (int q = tptr[k]; q < tptr[k + 1]; ++q) slot[trows[q]] = (k << kTileRowBits) | (q - tptr[k]);
+      Uploads up(((size_t)T + 1 + (size_t)m) * sizeof(int) + 2 * (size_t)T * sizeof(int) + 65536, s);
       P->ntiles = T;
       P->tile_ptr = t.get<int>(T + 1);
       P->tile_rows = t.get<int>(m);
       P->tile_slot = t.get<int>(m);
-      to_device(P->tile_ptr, tptr, s);
-      to_device(P->tile_rows, trows, s);
-      to_device(P->tile_slot, slot, s);
+      up.put(P->tile_ptr, tptr);
+      up.put(P->tile_rows, trows);
+      hipck(launch_fill_i32(P->tile_slot, -1, m, s));
+      hipck(launch_tile_slot(P->tile_ptr, P->tile_rows, T, P->tile_slot, s));
       const TileSet ts{P->tile_ptr, P->tile_rows, P->tile_slot};
-      int* tcnt = t.get<int>(T);
+      // fine rows of every tile: counts (and the largest |R_I| and row lengths), a scan, the fill
+      int* tcnt = t.get<int>(T + 1);
       int* trmax = t.get<int>(2 * (size_t)T);
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, false, tcnt, trmax, nullptr,
                              nullptr, PART_ALL, P->opt.nblocks, s));
-      std::vector<int> hcnt = to_host(tcnt, T, s);
-      std::vector<int> hrmax = to_host(trmax, 2 * (size_t)T, s);
+      P->tile_fptr = t.get<int>(T + 1);
+      scan(tcnt, T, P->tile_fptr);
+      PinnedBuf tb((3 * (size_t)T + 1) * sizeof(int), s);
+      hipck(hipMemcpyAsync(tb.as<int>(), P->tile_fptr, ((size_t)T + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+      if (T) hipck(hipMemcpyAsync(tb.as<int>() + T + 1, trmax, 2 * (size_t)T * sizeof(int), hipMemcpyDeviceToHost, s));
+      read_back(hsm, dflag, 1, s);
+      if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
       t.put(tcnt);
       t.put(trmax);
-      std::vector<int> fptr(T + 1, 0);
-      long long acc = 0;
-      for (int k = 0; k < T; ++k) {
-        acc += hcnt[k];
-        if (acc > INT32_MAX) fail(PTAP_ERR_TOO_LARGE);
-        fptr[k + 1] = (int)acc;
-      }
-      P->tile_fptr = t.get<int>(T + 1);
+      std::vector<int> fptr(tb.as<int>(), tb.as<int>() + T + 1);
+      const int* hrmax = tb.as<int>() + T + 1;
+      const long long acc = fptr[T];
       P->tile_fine = t.get<int>(acc);
-      to_device(P->tile_fptr, fptr, s);
       P->host_fptr = fptr;
       hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
                              P->tile_fptr, P->tile_fine, PART_ALL, P->opt.nblocks, s));
@@ -736,22 +961,18 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       // two-pass all-at-once (Alg. 8): the first pass walks only each tile's rows that own an
       // off-block entry there
       if (P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1) {
-        int* ocnt = t.get<int>(T);
+        int* ocnt = t.get<int>(T + 1);
         int* ormax = t.get<int>(2 * (size_t)T);
         hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, false, ocnt, ormax, nullptr,
                                nullptr, PART_OFF, P->opt.nblocks, s));
-        std::vector<int> hoc = to_host(ocnt, T, s);
+        P->off_fptr = t.get<int>(T + 1);
+        scan(ocnt, T, P->off_fptr);
+        read_back(hsm, dflag, 6, s);
         t.put(ocnt);
         t.put(ormax);
-        std::vector<int> ofptr(T + 1, 0);
-        long long oacc = 0;
-        for (int k = 0; k < T; ++k) {
-          oacc += hoc[k];
-          ofptr[k + 1] = (int)oacc;  // at most acc, which fits
-        }
-        P->off_fptr = t.get<int>(T + 1);
+        long long oacc;
+        memcpy(&oacc, hsm + 4, sizeof(oacc));  // at most acc, which fits
         P->off_fine = t.get<int>(oacc);
-        to_device(P->off_fptr, ofptr, s);
         hipck(launch_tile_fine(pat, P->pt_ptr, P->pt_row, ts, T, r, true, nullptr, nullptr,
                                P->off_fptr, P->off_fine, PART_OFF, P->opt.nblocks, s));
         P->rows_formed += oacc;
@@ -852,7 +1073,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         tc.tile_global = std::get<2>(kv.first) != 0;
         tc.count = (int)kv.second.size();
         tc.tiles = t.get<int>(tc.count);
-        to_device(tc.tiles, kv.second, s);
+        up.put(tc.tiles, kv.second);
         tc.host_tiles = kv.second;
         // the short-row kernel pairs consecutive rows of a tile's list: order them by owned count
         if (tc.fast) {
@@ -905,7 +1126,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     P->fold_used = atomic ? PTAP_FOLD_ATOMIC : PTAP_FOLD_OWNER;
     if (atomic) {
       // Single-pass forms: rows with |R_I| <= 32, at most 32 entries in P(I,:) and at most 32 in
-      // every row of C under them take the short-row kernel; the others the general one.
+      // every row of C under them take the short-row kernel; the others the general one, by
+      // capacity class.  Rows with an empty P(I,:) or R_I add nothing and are dropped.
       const bool twopass = P->opt.algo == PTAP_ALLATONCE && P->opt.nblocks > 1;
       RowMulArgs gf{};
       gf.nX = gf.nY = n;
@@ -914,39 +1136,21 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       gf.nF = m;
       gf.nnzF = P->nnzC;
       const bool short_ok = !twopass && rowmul_short_fits(gf);
-      const std::vector<int>& hr = host_r();
-      const std::vector<int>& hP_rowptr = host_P_rowptr();
-      std::vector<int> hA_rowptr, hPc;
-      if (short_ok) {
-        hA_rowptr = to_host(pat.A_rowptr, (size_t)n + 1, s);
-        hPc = to_host(pat.P_col, (size_t)P->nnzP, s);
-      }
-      std::vector<int> rows, srows[2];
-      std::vector<long long> need;
-      for (int I = 0; I < n; ++I)
-        if (hP_rowptr[I + 1] > hP_rowptr[I] && hr[I] > 0) {
-          bool fits = short_ok && hr[I] <= kRowMulMaxLen &&
-                      hP_rowptr[I + 1] - hP_rowptr[I] <= kRowMulMaxLen;
-          for (int e = hP_rowptr[I]; fits && e < hP_rowptr[I + 1]; ++e)
-            fits = h_c_ptr[hPc[e] + 1] - h_c_ptr[hPc[e]] <= kRowMulMaxLen;
-          if (fits) {
-            srows[hA_rowptr[I + 1] - hA_rowptr[I] > kHalfLanes].push_back(I);
-          } else {
-            rows.push_back(I);
-            need.push_back(hr[I]);
-          }
-        }
-      P->arows = make_classes(t, rows, need, lmax, s);
+      int* code = t.get<int>(n);
+      hipck(launch_rowform_codes(2, n, r, pat.A_rowptr, P->C_rowptr, pat.P_rowptr, pat.P_col, short_ok, code, s));
+      int* sorted = nullptr;
+      const std::vector<int> hist = classes_from_codes(t, code, nullptr, n, kCodeShort1 + 1, &sorted, s);
+      t.put(code);
+      P->arows = cap_classes(hist, sorted, lmax);
+      long long kept = 0;
+      for (int v : hist) kept += v;
       for (int k = 0; k < 2; ++k) {
-        P->n_af_short[k] = (int)srows[k].size();
-        if (!srows[k].empty()) {
-          P->af_short[k] = t.get<int>(srows[k].size());
-          to_device(P->af_short[k], srows[k], s);
-        }
+        P->n_af_short[k] = hist[kCodeShort0 + k];
+        P->af_short[k] = group_rows(hist, sorted, kCodeShort0 + k);
       }
       spill_need_ints = spill_ints(P->arows, 1);
       spill_need_vals = spill_need_ints;
-      P->rows_formed = (int64_t)(rows.size() + srows[0].size() + srows[1].size()) * (twopass ? 2 : 1);
+      P->rows_formed = (int64_t)kept * (twopass ? 2 : 1);
       t.put(P->pt_ptr);
       t.put(P->pt_row);
       P->pt_ptr = P->pt_row = nullptr;
@@ -960,6 +1164,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     const std::vector<int>& hr = host_r();
     const std::vector<int>& hP_rowptr = host_P_rowptr();
     std::vector<int> hPcol = to_host(pat.P_col, (size_t)P->nnzP, s);
+    std::vector<int> h_c_ptr = to_host(P->C_rowptr, (size_t)m + 1, s);
     std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
     const int lds_max = lmax / 2 >= 64 ? lmax / 2 : 64;
     std::vector<int> mark(m, -1), frows, grows;

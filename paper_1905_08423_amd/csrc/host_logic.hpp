@@ -121,7 +121,6 @@ inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE,
       tglob.push_back(1);
       continue;
     }
-    const size_t start = trows.size();
     queue.clear();
     queue.push_back(seed);
     state[seed] = -2;
@@ -146,10 +145,13 @@ inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE,
       }
     }
     for (size_t q = head; q < queue.size(); ++q) state[queue[q]] = -1;  // not taken
-    std::sort(trows.begin() + (long)start, trows.end());
     tptr.push_back((int)trows.size());
     tglob.push_back(0);
   }
+  // list each tile's rows in ascending order: one pass over the range puts every row at the next
+  // free position of its tile
+  std::vector<int> pos(tptr.begin(), tptr.end() - 1);
+  for (int i = lo; i < hi; ++i) trows[pos[state[i]]++] = i;
 }
 
 // Multiplier of the short-row owner kernel's R_I hash (slot = top 6 bits of key * mul, linear
@@ -163,7 +165,7 @@ inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE,
 // half-wavefront meet less often), and measured at 128^3 a candidate with 8% fewer probes ran 9%
 // slower.  Candidates and sample are fixed (the candidates come from splitmix64 with a fixed
 // seed), so a plan gets the same multiplier on every machine.
-inline unsigned choose_hash_mul(int m, const std::vector<int>& cptr, const std::vector<int>& ccol) {
+inline unsigned choose_hash_mul(int m, const int* cptr, const int* ccol) {
   constexpr int kCands = 16, kSample = 512, kSlots = 64, kShift = 26, kMaxKeys = 32;
   unsigned cand[kCands];
   cand[0] = 0x9E3779B1u;
@@ -214,8 +216,8 @@ inline unsigned choose_hash_mul(int m, const std::vector<int>& cptr, const std::
 // All rows of C in tiles: the rows are split into up to kGrowParts contiguous ranges of at least
 // kGrowPartRows rows, grown on threads of their own, and the ranges' tiles listed in range order.
 // The split depends on m only, so the tiles are the same on every machine.
-constexpr int kGrowParts = 8;
-constexpr int kGrowPartRows = 32768;
+constexpr int kGrowParts = 16;
+constexpr int kGrowPartRows = 16384;
 
 inline void grow_tiles(int m, const int* cptr, const int* ccol, int TE, int TR, std::vector<int>& tptr,
                 std::vector<int>& trows, std::vector<char>& tglob) {

@@ -54,15 +54,12 @@ constexpr int kXcds = 8;                // accelerator complex dies of the MI355
 // ---------------------------------------------------------------------------------------
 // Launch wrappers (kernels.hip).  All take a stream and return hipError_t.
 // ---------------------------------------------------------------------------------------
-hipError_t launch_validate(const int* rowptr, const int* col, int nrows, int ncols, long long nnz,
-                           int* err, hipStream_t s);
 hipError_t launch_fill_i32(int* p, int value, long long count, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double value, long long count, hipStream_t s);
 hipError_t launch_stream_sum(const double* x, long long n, double* out, hipStream_t s);
 hipError_t launch_count_cols(const int* col, long long nnz, int* cnt, hipStream_t s);
 hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, int* cursor,
                                  int* t_row, int* t_pos, hipStream_t s);
-hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s);  // min(w_I, m)
 // out[0..4]: needed rows, fold terms, max |R_I|, max(nnz(P(I,:)), nnz(A(I,:))), products
 // A(I,J) P(J,j) of the needed rows (the sum of w over them); out zeroed by the caller
 hipError_t launch_row_stats(const Patterns& p, const int* r, const int* w, unsigned long long* out,
@@ -88,6 +85,46 @@ hipError_t launch_tile_fine(const Patterns& p, const int* pt_ptr, const int* pt_
 // tile owns.
 hipError_t launch_tile_order(const Patterns& p, const int* tiles, int ntiles, const int* fptr,
                              int* fine, const int* slot, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------
+// Device symbolic building blocks (symbolic.hip).
+// ---------------------------------------------------------------------------------------
+// Exclusive prefix sum of n int counts into out[0..n] (out[n] = total; out may alias in).
+// scratch: scan_scratch_count(n) int64 values, the last of which receives the total; *flag |= 1
+// if the total exceeds INT32_MAX.
+size_t scan_scratch_count(long long n);
+hipError_t launch_scan_i32(const int* in, long long n, int* out, long long* scratch, int* flag,
+                           hipStream_t s);
+// Row classes by a stable counting sort over codes in [0, nbins) (negative: dropped); item k is
+// row list[k] (or k).  sorted: count ints; hist: nbins ints (group sizes, groups in code order);
+// scratch: class_scratch_ints(count, nbins) ints; scan_scratch as for launch_scan_i32 over
+// nbins * ceil(count / 256) cells.
+constexpr int kMaxClassBins = 64;
+constexpr int kCodeShort0 = 31;  // row-form short lists (rows of X with <= kHalfLanes entries)
+constexpr int kCodeShort1 = 32;  // (longer rows of X)
+size_t class_scratch_ints(int count, int nbins);
+hipError_t launch_class_build(const int* code, const int* list, int count, int nbins, int* scratch,
+                              long long* scan_scratch, int* flag, int* sorted, int* hist, hipStream_t s);
+// code[k] = log2 of the hash capacity for need[list[k]] keys (list null: need[k]), -1 if <= 0.
+hipError_t launch_cap_codes_i32(const int* need, const int* list, int count, int* code, hipStream_t s);
+hipError_t launch_cap_codes_i64(const long long* need, const int* list, int count, int* code, hipStream_t s);
+// Pattern checks; err and cnt[0..1] zeroed by the caller.  Valid iff err == 0 and cnt[0] == cnt[1].
+hipError_t launch_validate_pattern(const int* rowptr, const int* col, int nrows, int ncols, long long nnz,
+                                   int* err, unsigned long long* cnt, hipStream_t s);
+// |R_I| and min(w_I, m) of every fine row; rows whose product count could overflow the one-pass
+// table get r = 0 and are appended to ovf (*novf zeroed by the caller).
+hipError_t launch_ap_count(const Patterns& p, int* r, int* w, int* ovf, int* novf, hipStream_t s);
+// C's pattern by the two-level union: count pass (cnt, flag, ovf / novf for rows left to the
+// class launches) or fill pass (rows not flagged).
+hipError_t launch_c_two_level(const Patterns& p, const int* pt_ptr, const int* pt_row, bool fill, int* cnt,
+                              unsigned char* flag, int* ovf, int* novf, const int* C_rowptr, int* C_col,
+                              hipStream_t s);
+hipError_t launch_c_bound_list(const int* pt_ptr, const int* pt_row, const int* r, const int* list, int count,
+                               int m, long long* bound, hipStream_t s);
+hipError_t launch_tile_slot(const int* tptr, const int* trows, int ntiles, int* slot, hipStream_t s);
+// Launch-class codes of the row-form kernels; mode 0: rows of AP, 1: rows of C, 2: atomic fold.
+hipError_t launch_rowform_codes(int mode, int nrows, const int* r, const int* x_ptr, const int* c_ptr,
+                                const int* P_rowptr, const int* P_col, bool short_ok, int* code, hipStream_t s);
 
 struct NumericArgs {
   Patterns p;

@@ -37,34 +37,6 @@ __device__ __forceinline__ int* gkeys(int* gtab, int cap, int w) { return gtab +
 // Utilities
 // =============================================================================================
 
-__global__ void k_validate(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
-                           int ncols, long long nnz, int* err) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r == 0 && (rowptr[0] != 0 || (long long)rowptr[nrows] != nnz)) atomicOr(err, 1);
-  if (r >= nrows) return;
-  const long long b = rowptr[r], e = rowptr[r + 1];
-  if (b < 0 || e < b || e > nnz) {
-    atomicOr(err, 2);
-    return;
-  }
-  int prev = -1;
-  for (long long k = b; k < e; ++k) {
-    const int c = col[k];
-    if (c <= prev || c >= ncols) {
-      atomicOr(err, 4);
-      return;
-    }
-    prev = c;
-  }
-}
-
-hipError_t launch_validate(const int* rowptr, const int* col, int nrows, int ncols, long long nnz,
-                           int* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(nrows, 256)), dim3(256), 0, s, rowptr, col, nrows,
-                     ncols, nnz, err);
-  return hipGetLastError();
-}
-
 template <class T>
 __global__ void k_fill(T* p, T value, long long count) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
@@ -150,49 +122,27 @@ hipError_t launch_transpose_fill(const int* rowptr, const int* col, int nrows, i
   return hipGetLastError();
 }
 
-// w_I = sum over J in row I of A of nnz(P(J,:)): the number of products of row I of AP, an
-// upper bound on |R_I|.
-// w[I] = min(sum_{J in A(I,:)} nnz(P(J,:)), m): the product count of row I of AP, which bounds
-// |R_I| (at most m distinct columns).
-__global__ void k_row_work(Patterns p, int* w) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= p.n) return;
-  long long s = 0;
-  for (int k = p.A_rowptr[I]; k < p.A_rowptr[I + 1]; ++k) {
-    const int J = p.A_col[k];
-    s += p.P_rowptr[J + 1] - p.P_rowptr[J];
-  }
-  w[I] = (int)(s < p.m ? s : p.m);
-}
-
-hipError_t launch_row_work(const Patterns& p, int* w, hipStream_t s) {
-  if (p.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_work, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, w);
-  return hipGetLastError();
-}
-
 // Fine-row statistics of a plan, reduced over all rows: out[0] counts the rows with P(I,:) and R_I
 // both non-empty (the rows the fold needs), out[1] = sum_I nnz(P(I,:)) |R_I| (fold terms),
 // out[2] = max_I |R_I|, out[3] = max_I max(nnz(P(I,:)), nnz(A(I,:))).  out holds zeros on entry.
-// Launched with 256 threads per block.
+// Launched with 256 threads per block, grid-stride over the rows.
 __global__ void k_row_stats(Patterns p, const int* __restrict__ r, const int* __restrict__ w,
                             unsigned long long* out) {
   __shared__ unsigned long long sh[5][256];
   const int t = threadIdx.x;
-  const int I = blockIdx.x * blockDim.x + t;
   unsigned long long v[5] = {0, 0, 0, 0, 0};
-  if (I < p.n) {
+  for (long long I = blockIdx.x * (long long)blockDim.x + t; I < p.n; I += (long long)gridDim.x * blockDim.x) {
     const int lp = p.P_rowptr[I + 1] - p.P_rowptr[I];
     const int la = p.A_rowptr[I + 1] - p.A_rowptr[I];
     const int rI = r[I];
     if (lp > 0 && rI > 0) {
-      v[0] = 1;
-      v[1] = (unsigned long long)lp * (unsigned long long)rI;
-      v[4] = (unsigned long long)w[I];
+      v[0] += 1;
+      v[1] += (unsigned long long)lp * (unsigned long long)rI;
+      v[4] += (unsigned long long)w[I];
     }
-    v[2] = rI > 0 ? (unsigned long long)rI : 0;
+    v[2] = max(v[2], rI > 0 ? (unsigned long long)rI : 0ULL);
     const int l = lp > la ? lp : la;
-    v[3] = l > 0 ? (unsigned long long)l : 0;
+    v[3] = max(v[3], l > 0 ? (unsigned long long)l : 0ULL);
   }
   for (int q = 0; q < 5; ++q) sh[q][t] = v[q];
   __syncthreads();
@@ -218,7 +168,8 @@ __global__ void k_row_stats(Patterns p, const int* __restrict__ r, const int* __
 hipError_t launch_row_stats(const Patterns& p, const int* r, const int* w, unsigned long long* out,
                             hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_stats, dim3(grid_for(p.n, 256)), dim3(256), 0, s, p, r, w, out);
+  // grid-stride over at most 1024 workgroups: few same-address atomics at the end
+  hipLaunchKernelGGL(k_row_stats, dim3(grid_for(p.n, 256, 1024)), dim3(256), 0, s, p, r, w, out);
   return hipGetLastError();
 }
 

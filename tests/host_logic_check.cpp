@@ -154,17 +154,17 @@ int main() {
   std::printf("ok capacities\n");
 
   std::vector<int> ptr, col;
-  stencil27(40, ptr, col);  // 64,000 rows: one range
+  stencil27(40, ptr, col);  // 64,000 rows: three ranges
   check_tiles("27pt_40", 40 * 40 * 40, ptr, col, 3049, 1024);
   const unsigned golden = 0x9E3779B1u;
-  stencil27(64, ptr, col);  // 262,144 rows: eight ranges
+  stencil27(64, ptr, col);  // 262,144 rows: sixteen ranges
   check_tiles("27pt_64", 64 * 64 * 64, ptr, col, 3049, 1024);
   check_tiles("27pt_64_small_tiles", 64 * 64 * 64, ptr, col, 200, 16);
-  const unsigned mul64 = choose_hash_mul(64 * 64 * 64, ptr, col);
+  const unsigned mul64 = choose_hash_mul(64 * 64 * 64, ptr.data(), col.data());
   if (mul64 != golden) fail("hash multiplier at 64^3 is not the golden ratio", mul64);
   std::printf("ok hash multiplier 64^3 keeps the golden ratio\n");
 
-  // a chain of 100,003 rows: three ranges of unequal size
+  // a chain of 100,003 rows: six ranges of unequal size
   {
     const int m = 100003;
     ptr.assign(m + 1, 0);
@@ -204,7 +204,7 @@ int main() {
   // the hash multiplier: the golden ratio crowds the keys of a 108^3 coarse grid; rows longer
   // than the short-row limit are not scored
   stencil27(108, ptr, col);
-  const unsigned mul108 = choose_hash_mul(108 * 108 * 108, ptr, col);
+  const unsigned mul108 = choose_hash_mul(108 * 108 * 108, ptr.data(), col.data());
   if (mul108 == golden || (mul108 & 1u) == 0) fail("hash multiplier at 108^3", mul108);
   std::printf("ok hash multiplier 108^3 replaces the golden ratio (0x%08x)\n", mul108);
   {
@@ -215,8 +215,8 @@ int main() {
       std::sort(c2.end() - 40, c2.end());
       p2[r + 1] = (int)c2.size();
     }
-    if (choose_hash_mul(m, p2, c2) != golden) fail("hash multiplier with only long rows");
-    if (choose_hash_mul(0, std::vector<int>(1, 0), std::vector<int>()) != golden)
+    if (choose_hash_mul(m, p2.data(), c2.data()) != golden) fail("hash multiplier with only long rows");
+    if (choose_hash_mul(0, std::vector<int>(1, 0).data(), nullptr) != golden)
       fail("hash multiplier with no rows");
   }
   std::printf("ok hash multiplier edge cases\n");
