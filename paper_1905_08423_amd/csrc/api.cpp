@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <exception>
 #include <map>
 #include <mutex>
@@ -115,55 +116,6 @@ void to_device(T* d, const std::vector<T>& h, hipStream_t s) {
   }
 }
 
-// Group rows by table capacity, by a stable counting sort over the capacity's exponent: row(k)
-// with the key-count bound need(k), k = 0 .. count-1, rows in ascending order.  Rows with a bound
-// of zero are dropped (they add nothing).  Capacities above `lds_max` go to device-memory tables.
-template <class Row, class Need>
-std::vector<RowClass> make_classes_by(Tracker& t, size_t count, Row row, Need need, int lds_max,
-                                      hipStream_t s) {
-  constexpr int kBins = 31;
-  std::vector<unsigned char> bin(count);
-  size_t cnt[kBins] = {};
-  for (size_t k = 0; k < count; ++k) {
-    const long long v = need(k);
-    if (v <= 0) {
-      bin[k] = 0xFF;
-      continue;
-    }
-    bin[k] = (unsigned char)cap_log2(v);
-    ++cnt[bin[k]];
-  }
-  size_t off[kBins + 1] = {};
-  for (int b = 0; b < kBins; ++b) off[b + 1] = off[b] + cnt[b];
-  std::vector<int> sorted(off[kBins]);
-  {
-    size_t pos[kBins];
-    std::copy(off, off + kBins, pos);
-    for (size_t k = 0; k < count; ++k)
-      if (bin[k] != 0xFF) sorted[pos[bin[k]]++] = row(k);
-  }
-  std::vector<RowClass> out;
-  for (int b = 0; b < kBins; ++b) {
-    if (!cnt[b]) continue;
-    RowClass rc;
-    rc.cap = 1 << b;
-    rc.global = rc.cap > lds_max;
-    rc.count = (int)cnt[b];
-    rc.rows = t.get<int>(cnt[b]);
-    hipck(hipMemcpyAsync(rc.rows, sorted.data() + off[b], cnt[b] * sizeof(int), hipMemcpyHostToDevice, s));
-    out.push_back(rc);
-  }
-  hipck(hipStreamSynchronize(s));  // `sorted` goes out of scope
-  return out;
-}
-
-// The listed rows, with their bounds.
-std::vector<RowClass> make_classes(Tracker& t, const std::vector<int>& rows,
-                                   const std::vector<long long>& need, int lds_max, hipStream_t s) {
-  return make_classes_by(
-      t, rows.size(), [&](size_t k) { return rows[k]; }, [&](size_t k) { return need[k]; }, lds_max, s);
-}
-
 size_t spill_ints(const std::vector<RowClass>& cls, int per_slot_ints) {
   size_t need = 0;
   for (auto& c : cls)
@@ -252,36 +204,6 @@ struct Uploads {
     used = (used + b + 255) & ~(size_t)255;
   }
 };
-
-// Runs side() on a thread of its own (here, if no thread can start) while main() runs here;
-// rethrows what either threw once both are done.
-template <class F, class G>
-void run_beside(F&& side, G&& main_part) {
-  std::exception_ptr err;
-  auto wrapped = [&] {
-    try {
-      side();
-    } catch (...) {
-      err = std::current_exception();
-    }
-  };
-  std::thread th;
-  bool started = false;
-  try {
-    th = std::thread(wrapped);
-    started = true;
-  } catch (...) {
-  }
-  if (!started) wrapped();
-  try {
-    main_part();
-  } catch (...) {
-    if (started) th.join();
-    throw;
-  }
-  if (started) th.join();
-  if (err) std::rethrow_exception(err);
-}
 
 // Device classes from per-item codes (launch_class_build): the group sizes, read back after one
 // wait, and the rows of all groups in one allocation (*sorted; null if no row is kept).  The
@@ -619,13 +541,6 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   hipck(launch_fill_i32(dflag, 0, 8, s));
   PinnedBuf small(4096, s);
   int* hsm = small.as<int>();
-  // Host copies of P's row pointers and of |R_I| (8 MB each at 128^3), made only by the branches
-  // that walk them row by row.
-  std::vector<int> hP_store, hr_store;
-  auto host_P_rowptr = [&]() -> const std::vector<int>& {
-    if (hP_store.size() != (size_t)n + 1) hP_store = to_host(pat.P_rowptr, (size_t)n + 1, s);
-    return hP_store;
-  };
   auto scan = [&](const int* in, long long count, int* out) {
     long long* sc = t.get<long long>(scan_scratch_count(count));
     hipck(launch_scan_i32(in, count, out, sc, dflag, s));
@@ -652,48 +567,67 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // outgrow its table go to launches by capacity class, sized by w_I.
   int* r = t.get<int>(n);
   int* w = t.get<int>(n);
+  int* ap_ovf = t.get<int>(n);
   int* c_cnt = nullptr;
   unsigned char* c_flag = nullptr;
   int* c_ovf = nullptr;
   int n_c_ovf = 0;
   int rmax_all = 0, pmax_all = 0;
-  {
-    int* ovf = t.get<int>(n);
-    hipck(launch_ap_count(pat, r, w, ovf, dflag + 1, s));
-    // --- Merged / all-at-once: count pass of C's pattern by the two-level union (needs no R_I)
-    if (!two) {
-      c_cnt = t.get<int>(m + 1);
-      c_flag = t.get<unsigned char>(m);
-      c_ovf = t.get<int>(m);
-      hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, false, c_cnt, c_flag, c_ovf, dflag + 2,
-                               nullptr, nullptr, s));
-    }
-    read_back(hsm, dflag, 4, s);
-    if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
-    const int novf = hsm[1];
-    n_c_ovf = hsm[2];
+  // merged / all-at-once with tiles to grow: C's fill pass runs range by range in the owner branch,
+  // and |R_I| is formed on the device while the host grows the tiles
+  const bool fill_by_range = !two && !blk && P->opt.fold != PTAP_FOLD_ATOMIC;
+  bool r_done = false;
+  // Counters for the statistics (rows needed, fold terms sum_I nnz(P(I,:)) |R_I|, longest rows,
+  // products), reduced on the device once |R_I| is known; read back into hsm[8..17].
+  unsigned long long* st = t.get<unsigned long long>(5);
+  hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
+  auto launch_r = [&] { hipck(launch_ap_count(pat, r, w, ap_ovf, dflag + 1, s)); };
+  // after a read of dflag: rows the one-pass table could not hold, then the statistics
+  auto finish_r = [&](int novf) {
     if (novf > 0) {
-      std::vector<RowClass> cls = make_classes_dev(t, w, ovf, novf, P->lds_keys_max, s);
+      std::vector<RowClass> cls = make_classes_dev(t, w, ap_ovf, novf, P->lds_keys_max, s);
       size_t gi = spill_ints(cls, 2);  // keys + list (cap/2), rounded up
       int* gtab = gi ? t.get<int>(gi) : nullptr;
       for (auto& c : cls) hipck(launch_ap_row_count(pat, c, r, gtab, s));
       put_classes(t, cls);
       t.put(gtab);
     }
-    t.put(ovf);
-  }
-
-  auto host_r = [&]() -> const std::vector<int>& {
-    if (hr_store.size() != (size_t)n) hr_store = to_host(r, n, s);
-    return hr_store;
+    t.put(ap_ovf);
+    hipck(launch_row_stats(pat, r, w, st, s));
+    t.put(w);
+    hipck(hipMemcpyAsync(hsm + 8, st, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    r_done = true;
   };
-
-  // --- Counters for the statistics (rows needed, fold terms sum_I nnz(P(I,:)) |R_I|, longest
-  // rows, products), reduced on the device and read with nnz(C) below.
-  unsigned long long* st = t.get<unsigned long long>(5);
-  hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
-  hipck(launch_row_stats(pat, r, w, st, s));
-  t.put(w);
+  // after the read that follows finish_r
+  auto take_stats = [&](bool bounds_too) {
+    unsigned long long h[5];
+    memcpy(h, hsm + 8, sizeof(h));
+    P->rows_needed = (long long)h[0];
+    P->fold_terms = (long long)h[1];
+    P->products = (long long)h[4];
+    if (bounds_too) {
+      rmax_all = (int)h[2];
+      pmax_all = (int)h[3];
+    }
+  };
+  if (!fill_by_range) launch_r();
+  // --- Merged / all-at-once: count pass of C's pattern by the two-level union (needs no R_I)
+  if (!two) {
+    c_cnt = t.get<int>(m + 1);
+    c_flag = t.get<unsigned char>(m);
+    c_ovf = t.get<int>(m);
+    hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, false, c_cnt, c_flag, c_ovf, dflag + 2,
+                             nullptr, nullptr, 0, m, s));
+  }
+  read_back(hsm, dflag, 4, s);
+  if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+  n_c_ovf = hsm[2];
+  if (fill_by_range && n_c_ovf > 0) {
+    // the rows of C the union left are sized by sum |R_I|: form R_I now
+    launch_r();
+    read_back(hsm, dflag, 4, s);
+  }
+  if (!fill_by_range || n_c_ovf > 0) finish_r(hsm[1]);
 
   // --- Two-step: the stored pattern of AP (rows sorted).
   if (two) {
@@ -746,19 +680,25 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     }
     P->C_rowptr = t.get<int>(m + 1);
     scan(c_cnt, m, P->C_rowptr);
+    unsigned* bnd = nullptr;
+    if (!r_done) {
+      // the tile size needs bounds on |R_I| and the row lengths before R_I is formed
+      bnd = t.get<unsigned>(2);
+      hipck(launch_fill_i32(reinterpret_cast<int*>(bnd), 0, 2, s));
+      hipck(launch_row_bounds(pat, P->C_rowptr, bnd, s));
+      hipck(hipMemcpyAsync(hsm + 20, bnd, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    }
     read_back(hsm, dflag, 6, s);
-    unsigned long long h[5];
-    read_back(reinterpret_cast<unsigned long long*>(hsm + 8), st, 5, s);
-    memcpy(h, hsm + 8, sizeof(h));
-    t.put(st);
     if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+    if (r_done) {
+      take_stats(true);
+    } else {
+      rmax_all = hsm[20];
+      pmax_all = hsm[21];
+      t.put(bnd);
+    }
     long long acc;
     memcpy(&acc, hsm + 4, sizeof(acc));
-    P->rows_needed = (long long)h[0];
-    P->fold_terms = (long long)h[1];
-    rmax_all = (int)h[2];
-    pmax_all = (int)h[3];
-    P->products = (long long)h[4];
     P->nnzC = acc;
     P->C_col = t.get<int>(acc);
     if (two) {
@@ -771,8 +711,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       put_classes(t, cls);
       t.put(gtab);
     } else {
-      hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
-                               P->C_rowptr, P->C_col, s));
+      // rows the two-level union left first; the others here, or by row range in the owner branch
+      // below, where each range's tiles grow on the host as soon as its rows are filled and copied
       if (n_c_ovf > 0) {
         std::vector<RowClass> cls = make_classes_dev(t, c_cnt, c_ovf, n_c_ovf, P->lds_keys_max, s);
         size_t gi = spill_ints(cls, 2);
@@ -783,9 +723,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         put_classes(t, cls);
         t.put(gtab);
       }
+      if (!fill_by_range)
+        hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
+                                 P->C_rowptr, P->C_col, 0, m, s));
     }
     t.put(c_cnt);
-    t.put(c_flag);
     t.put(c_ovf);
     P->pattern_bytes = (int64_t)(m + 1 + acc) * (int64_t)sizeof(int);
   }
@@ -867,12 +809,33 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     // whichever the cost model of the two folds (host_logic.hpp fold_estimate) estimates faster.
     bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
     if (!atomic) {
-      // C's pattern on the host for growing the tiles (one copy into page-locked memory)
+      // C's pattern on the host for growing the tiles (page-locked memory): the row pointers
+      // first, then the columns range by range, each range's tiles growing as soon as its
+      // columns have arrived
       PinnedBuf cbuf(((size_t)m + 1 + (size_t)P->nnzC) * sizeof(int), s);
       int* h_c_ptr = cbuf.as<int>();
       int* h_c_col = h_c_ptr + m + 1;
-      if (P->nnzC) hipck(hipMemcpyAsync(h_c_col, P->C_col, (size_t)P->nnzC * sizeof(int), hipMemcpyDeviceToHost, s));
       read_back(h_c_ptr, P->C_rowptr, (size_t)m + 1, s);
+      const int nparts = grow_parts(m);
+      std::vector<hipEvent_t> arrived(nparts, nullptr);
+      struct EventsGuard {
+        std::vector<hipEvent_t>& e;
+        ~EventsGuard() {
+          for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } events_guard{arrived};
+      for (int q = 0; q < nparts; ++q) {
+        int lo, hi;
+        grow_range_bounds(m, nparts, q, lo, hi);
+        hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
+                                 P->C_rowptr, P->C_col, lo, hi, s));
+        const size_t b = (size_t)h_c_ptr[lo], e = (size_t)h_c_ptr[hi];
+        if (e > b)
+          hipck(hipMemcpyAsync(h_c_col + b, P->C_col + b, (e - b) * sizeof(int), hipMemcpyDeviceToHost, s));
+        hipck(hipEventCreateWithFlags(&arrived[q], hipEventDisableTiming));
+        hipck(hipEventRecord(arrived[q], s));
+      }
       // Tiles of rows of C held in LDS.  Tiles whose fine rows are short (|R_I| and
       // the rows of P within the short-row limits) take the short-row kernel; the tile size is
       // set by that kernel's LDS layout when every row qualifies.
@@ -921,9 +884,39 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       P->TE = TE;
       std::vector<int> tptr, trows;
       std::vector<char> tglob;
-      // the hash multiplier is chosen on a thread of its own while the tiles grow
-      run_beside([&] { P->hash_mul = choose_hash_mul(m, h_c_ptr, h_c_col); },
-                 [&] { grow_tiles(m, h_c_ptr, h_c_col, TE, TR, tptr, trows, tglob); });
+      // |R_I| on the device while the tiles grow on the host
+      if (!r_done) launch_r();
+      std::atomic<int> copy_err{0};
+      grow_tiles(m, h_c_ptr, h_c_col, TE, TR, tptr, trows, tglob, [&](int q) {
+        if (hipEventSynchronize(arrived[q]) != hipSuccess) copy_err = 1;
+      });
+      if (copy_err) hipck(hipErrorUnknown);
+      const bool stats_pending = !r_done;
+      if (!r_done) {
+        read_back(hsm, dflag, 4, s);
+        finish_r(hsm[1]);
+      }
+      // the hash multiplier is chosen on a thread of its own while the device works on the tiles
+      std::exception_ptr mul_err;
+      std::thread mul_thread;
+      auto pick_mul = [&] {
+        try {
+          P->hash_mul = choose_hash_mul(m, h_c_ptr, h_c_col);
+        } catch (...) {
+          mul_err = std::current_exception();
+        }
+      };
+      try {
+        mul_thread = std::thread(pick_mul);
+      } catch (...) {
+        pick_mul();  // no thread to spare
+      }
+      struct Joiner {
+        std::thread& th;
+        ~Joiner() {
+          if (th.joinable()) th.join();
+        }
+      } mul_join{mul_thread};
       const int T = (int)tglob.size();
       if (T >= (1 << (31 - kTileRowBits))) fail(PTAP_ERR_TOO_LARGE);
       Uploads up(((size_t)T + 1 + (size_t)m) * sizeof(int) + 2 * (size_t)T * sizeof(int) + 65536, s);
@@ -948,6 +941,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       if (T) hipck(hipMemcpyAsync(tb.as<int>() + T + 1, trmax, 2 * (size_t)T * sizeof(int), hipMemcpyDeviceToHost, s));
       read_back(hsm, dflag, 1, s);
       if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
+      if (stats_pending) take_stats(false);
       t.put(tcnt);
       t.put(trmax);
       std::vector<int> fptr(tb.as<int>(), tb.as<int>() + T + 1);
@@ -1086,6 +1080,8 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
           spill_need_ints = std::max(spill_need_ints, (size_t)tc.count * kWavesPerBlock * tc.cap);
         P->tclasses.push_back(tc);
       }
+      if (mul_thread.joinable()) mul_thread.join();
+      if (mul_err) std::rethrow_exception(mul_err);
       spill_need_vals = spill_need_ints;
       // numeric cache: only the short-row kernel reads it; the start must fit in 26 bits
       bool any_fast = false;
@@ -1158,52 +1154,36 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   }
 
   // --- Adjoint row classes.  U_I has the distinct columns of the rows of C under P(I,:) as keys
-  // (R_I's columns are among them); they are counted exactly on the host.  Rows whose rows of C
-  // under P(I,:) hold at most kAdjMaxWalk entries in total go to the short-row kernel.
+  // (R_I's columns are among them); they are counted on the device.  Rows whose rows of C under
+  // P(I,:) hold at most kAdjMaxWalk entries in total go to the short-row kernel.
   if (P->opt.backward) {
-    const std::vector<int>& hr = host_r();
-    const std::vector<int>& hP_rowptr = host_P_rowptr();
-    std::vector<int> hPcol = to_host(pat.P_col, (size_t)P->nnzP, s);
-    std::vector<int> h_c_ptr = to_host(P->C_rowptr, (size_t)m + 1, s);
-    std::vector<int> h_c_col = to_host(P->C_col, (size_t)P->nnzC, s);
     const int lds_max = lmax / 2 >= 64 ? lmax / 2 : 64;
-    std::vector<int> mark(m, -1), frows, grows;
-    std::vector<long long> fneed, gneed;
-    for (int I = 0; I < n; ++I) {
-      long long walk = 0, distinct = 0;
-      for (int e = hP_rowptr[I]; e < hP_rowptr[I + 1]; ++e) {
-        const int i = hPcol[e];
-        walk += h_c_ptr[i + 1] - h_c_ptr[i];
-        for (int c = h_c_ptr[i]; c < h_c_ptr[i + 1]; ++c)
-          if (mark[h_c_col[c]] != I) {
-            mark[h_c_col[c]] = I;
-            ++distinct;
-          }
-      }
-      const int np = hP_rowptr[I + 1] - hP_rowptr[I];
-      const long long need = std::max<long long>(std::max<long long>(distinct, hr[I]), 1);
-      // a row with an empty row of P contributes nothing (dA is zeroed before the launch)
-      if (np == 0) continue;
-      const int cap = cap_for(need);
-      if (np <= kAdjMaxSegs && walk <= kAdjMaxWalk && cap <= std::min(kAdjMaxCap, lds_max)) {
-        frows.push_back(I);
-        fneed.push_back(need);
-      } else {
-        grows.push_back(I);
-        gneed.push_back(need);
-      }
-    }
+    int* code = t.get<int>(n);
+    hipck(launch_adj_codes(pat, r, P->C_rowptr, P->C_col, std::min(kAdjMaxCap, lds_max), code, s));
+    int* sorted = nullptr;
+    const std::vector<int> hist = classes_from_codes(t, code, nullptr, n, kMaxClassBins, &sorted, s);
+    t.put(code);
     // the general kernel holds two tables of this capacity per wavefront
-    P->bwd_rows = make_classes(t, grows, gneed, lds_max, s);
+    P->bwd_rows = cap_classes(std::vector<int>(hist.begin(), hist.begin() + 31), sorted, lds_max);
     spill_need_ints = std::max(spill_need_ints, spill_ints(P->bwd_rows, 2));
     spill_need_vals = std::max(spill_need_vals, spill_ints(P->bwd_rows, 2));
-    for (RowClass& c : make_classes(t, frows, fneed, lds_max, s)) {
+    long long off = 0;
+    for (int b = 0; b < 32; ++b) off += hist[b];
+    for (int b = 32; b < kMaxClassBins; ++b) {
+      if (!hist[b]) continue;
+      RowClass c;
+      c.cap = 1 << (b - 32);
+      c.global = c.cap > lds_max;
       c.fast = true;
+      c.count = hist[b];
+      c.rows = sorted + off;
+      off += hist[b];
       P->bwd_rows.push_back(c);
     }
   }
-
   t.put(r);
+  t.put(c_flag);
+  t.put(st);
   P->spill_slots = std::max(spill_need_ints, spill_need_vals);
   if (spill_need_ints) P->gtab = t.get<int>(spill_need_ints);
   if (spill_need_vals) P->gval = t.get<double>(spill_need_vals);

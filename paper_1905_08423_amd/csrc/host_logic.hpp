@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <exception>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -219,16 +220,30 @@ inline unsigned choose_hash_mul(int m, const int* cptr, const int* ccol) {
 constexpr int kGrowParts = 16;
 constexpr int kGrowPartRows = 16384;
 
+inline int grow_parts(int m) { return (int)std::max<long long>(1, std::min<long long>(kGrowParts, m / kGrowPartRows)); }
+
+// Rows [lo, hi) of range p of grow_parts(m) ranges.
+inline void grow_range_bounds(int m, int parts, int p, int& lo, int& hi) {
+  lo = (int)((long long)m * p / parts);
+  hi = (int)((long long)m * (p + 1) / parts);
+}
+
+// A range reads only its own rows of C (cptr[lo..hi] and their columns), so a caller that copies
+// C's columns range by range passes wait_part(p), which returns once range p's columns are in
+// place; row pointers must all be in place on entry.
 inline void grow_tiles(int m, const int* cptr, const int* ccol, int TE, int TR, std::vector<int>& tptr,
-                std::vector<int>& trows, std::vector<char>& tglob) {
-  const int parts = (int)std::max<long long>(1, std::min<long long>(kGrowParts, m / kGrowPartRows));
+                std::vector<int>& trows, std::vector<char>& tglob,
+                const std::function<void(int)>& wait_part = std::function<void(int)>()) {
+  const int parts = grow_parts(m);
   std::vector<int> state(m, -1);
   std::vector<std::vector<int>> pp(parts), pr(parts);
   std::vector<std::vector<char>> pg(parts);
   std::vector<std::exception_ptr> err(parts);
   auto work = [&](int p) {
     try {
-      const int lo = (int)((long long)m * p / parts), hi = (int)((long long)m * (p + 1) / parts);
+      int lo, hi;
+      grow_range_bounds(m, parts, p, lo, hi);
+      if (wait_part) wait_part(p);
       grow_range(lo, hi, cptr, ccol, TE, TR, state.data(), pp[p], pr[p], pg[p]);
     } catch (...) {
       err[p] = std::current_exception();

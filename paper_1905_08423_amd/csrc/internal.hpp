@@ -114,14 +114,21 @@ hipError_t launch_validate_pattern(const int* rowptr, const int* col, int nrows,
 // |R_I| and min(w_I, m) of every fine row; rows whose product count could overflow the one-pass
 // table get r = 0 and are appended to ovf (*novf zeroed by the caller).
 hipError_t launch_ap_count(const Patterns& p, int* r, int* w, int* ovf, int* novf, hipStream_t s);
-// C's pattern by the two-level union: count pass (cnt, flag, ovf / novf for rows left to the
-// class launches) or fill pass (rows not flagged).
+// C's pattern by the two-level union over rows [row0, row1): count pass (cnt, flag, ovf / novf
+// for rows left to the class launches) or fill pass (rows not flagged).
 hipError_t launch_c_two_level(const Patterns& p, const int* pt_ptr, const int* pt_row, bool fill, int* cnt,
                               unsigned char* flag, int* ovf, int* novf, const int* C_rowptr, int* C_col,
-                              hipStream_t s);
+                              int row0, int row1, hipStream_t s);
 hipError_t launch_c_bound_list(const int* pt_ptr, const int* pt_row, const int* r, const int* list, int count,
                                int m, long long* bound, hipStream_t s);
 hipError_t launch_tile_slot(const int* tptr, const int* trows, int ntiles, int* slot, hipStream_t s);
+// out[0] = max over rows with P(I,:) non-empty of min over i in P(I,:) of |C(i,:)| (a bound on
+// |R_I|), out[1] = max over rows of max(nnz(P(I,:)), nnz(A(I,:))); out zeroed by the caller.
+hipError_t launch_row_bounds(const Patterns& p, const int* C_rowptr, unsigned* out, hipStream_t s);
+// Adjoint launch classes: code[I] = log2 of the table capacity (general kernel), 32 + that
+// (short-row kernel: tables of at most fast_cap slots), or -1 (empty P(I,:)).
+hipError_t launch_adj_codes(const Patterns& p, const int* r, const int* C_rowptr, const int* C_col, int fast_cap,
+                            int* code, hipStream_t s);
 // Launch-class codes of the row-form kernels; mode 0: rows of AP, 1: rows of C, 2: atomic fold.
 hipError_t launch_rowform_codes(int mode, int nrows, const int* r, const int* x_ptr, const int* c_ptr,
                                 const int* P_rowptr, const int* P_col, bool short_ok, int* code, hipStream_t s);

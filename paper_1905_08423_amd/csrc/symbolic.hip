@@ -292,129 +292,118 @@ hipError_t launch_validate_pattern(const int* rowptr, const int* col, int nrows,
 }
 
 // =============================================================================================
-// |R_I| and w_I in one pass (Alg. 1 / Alg. 2): one wavefront per fine row I forms the key set of
-// row I of AP in an LDS table of kApCap slots.  w_I, the number of products A(I,J) P(J,j), bounds
-// |R_I|; a row with w_I above kApMaxW could overflow the table and is listed in `ovf` instead
-// (its |R_I| comes from the launches by capacity class).  w[I] = min(w_I, m).
+// Inserting keys into a wavefront's LDS hash tables.  Each lane takes its own segment of `col`
+// ([s, s + l)), eight loads at a time; every round inserts at most one key per lane, and after a
+// round each table's count of keys grows by the new keys of the lanes that share it (`group`
+// masks them).  A table that passes `limit` keys stops taking keys (*ovf), so with limit + the
+// lanes of its group below its capacity, probing always finds a free slot.
 // =============================================================================================
-constexpr int kApCap = 256;
-constexpr int kApMaxW = kApCap - WAVE - 1;
+template <class Ins>
+__device__ __forceinline__ void insert_segments(int s, int l, const int* __restrict__ col,
+                                                unsigned long long group, int limit, int& occ, bool& ovf,
+                                                Ins&& ins) {
+  const int maxl = wave_max(l);
+  for (int e0 = 0; e0 < maxl; e0 += 8) {
+    int key[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) key[j] = e0 + j < l ? col[s + e0 + j] : -1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool fresh = key[j] >= 0 && !ovf && ins(key[j]);
+      occ += __popcll(ballot(fresh) & group);
+      ovf = ovf || occ > limit;
+    }
+  }
+}
+
+// =============================================================================================
+// |R_I| and w_I in one pass (Alg. 1 / Alg. 2): each half-wavefront forms the key set of one row
+// I of AP in a 64-slot LDS table, its lanes taking the entries J of A(I,:) and inserting the
+// columns of P(J,:).  A row with more than kApMaxKeys keys is listed in `ovf` instead (its |R_I|
+// comes from the launches by capacity class).  w[I] = min(w_I, m), w_I = sum of nnz(P(J,:)).
+// =============================================================================================
+constexpr int kApCap = 64;
+constexpr int kApMaxKeys = kApCap - 32 - 1;
 
 __global__ __launch_bounds__(kSymBlock) void k_ap_count(Patterns p, int* r, int* w, int* ovf, int* novf) {
-  __shared__ WaveScratch wsa[kSymWaves];
-  __shared__ int keys_all[kSymWaves][kApCap];
+  __shared__ int keys_all[2 * kSymWaves][kApCap];
   const int wid = threadIdx.x / WAVE, ln = lane();
-  const long long I64 = (long long)blockIdx.x * kSymWaves + wid;
-  if (I64 >= p.n) return;  // uniform over the wavefront
-  const int I = (int)I64;
-  WaveScratch* ws = wsa + wid;
-  int* keys = keys_all[wid];
-  const int a0 = p.A_rowptr[I], a1 = p.A_rowptr[I + 1];
+  const int h = ln >> 5, sub = ln & 31;
+  const long long I64 = ((long long)blockIdx.x * kSymWaves + wid) * 2 + h;
+  if (((long long)blockIdx.x * kSymWaves + wid) * 2 >= p.n) return;  // uniform over the wavefront
+  const bool live = I64 < p.n;
+  const int I = live ? (int)I64 : 0;
+  int* keys = keys_all[2 * wid + h];
+  keys[sub] = EMPTY;
+  keys[sub + 32] = EMPTY;
+  wave_sync();
+  const unsigned long long group = h ? 0xFFFFFFFF00000000ULL : 0x00000000FFFFFFFFULL;
+  const int a0 = live ? p.A_rowptr[I] : 0, la = live ? p.A_rowptr[I + 1] - a0 : 0;
+  const int maxa = wave_max(la);
   long long prod = 0;
-  for (int k = a0 + ln; k < a1; k += WAVE) {
-    const int J = p.A_col[k];
-    prod += p.P_rowptr[J + 1] - p.P_rowptr[J];
+  int occ = 0;
+  bool over = false;
+  for (int eb = 0; eb < maxa; eb += 32) {
+    int s = 0, l = 0;
+    if (eb + sub < la) {
+      const int J = p.A_col[a0 + eb + sub];
+      s = p.P_rowptr[J];
+      l = p.P_rowptr[J + 1] - s;
+    }
+    prod += l;
+    insert_segments(s, l, p.P_col, group, kApMaxKeys, occ, over, [&](int key) {
+      bool fresh;
+      hs_insert<false>(keys, kApCap - 1, 32 - 6, key, fresh);
+      return fresh;
+    });
   }
 #pragma unroll
-  for (int d = WAVE / 2; d > 0; d >>= 1) prod += __shfl_xor(prod, d, WAVE);
-  if (ln == 0) w[I] = (int)(prod < p.m ? prod : p.m);
-  if (prod > kApMaxW) {
-    if (ln == 0) {
-      r[I] = 0;
-      ovf[atomicAdd(novf, 1)] = I;
-    }
-    return;
+  for (int d = 16; d > 0; d >>= 1) prod += __shfl_xor(prod, d, WAVE);  // within the half
+  if (live && sub == 0) {
+    w[I] = (int)(prod < p.m ? prod : p.m);
+    r[I] = over ? 0 : occ;
+    if (over) ovf[atomicAdd(novf, 1)] = I;
   }
-  for (int q = ln; q < kApCap; q += WAVE) keys[q] = EMPTY;
-  wave_sync();
-  constexpr unsigned mask = kApCap - 1;
-  constexpr int shift = 32 - 8;  // log2(kApCap) = 8
-  static_assert(kApCap == 256, "shift assumes 256 slots");
-  int fresh_cnt = 0;
-  for_products(a0, a1, p.A_col, nullptr, p.P_rowptr, ws, [&](int k, double) {
-    bool fresh;
-    hs_insert<false>(keys, mask, shift, p.P_col[k], fresh);
-    fresh_cnt += fresh ? 1 : 0;
-  });
-  fresh_cnt = wave_sum(fresh_cnt);
-  if (ln == 0) r[I] = fresh_cnt;
 }
 
 hipError_t launch_ap_count(const Patterns& p, int* r, int* w, int* ovf, int* novf, hipStream_t s) {
   if (p.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ap_count, dim3(blocks_for(p.n, kSymWaves)), dim3(kSymBlock), 0, s, p, r, w, ovf, novf);
+  hipLaunchKernelGGL(k_ap_count, dim3(blocks_for(p.n, 2 * kSymWaves)), dim3(kSymBlock), 0, s, p, r, w, ovf, novf);
   return hipGetLastError();
 }
 
 // =============================================================================================
 // Pattern of C by a two-level union (Eq. allatoncerow): C(i,:) is the union over I with P(I,i)
 // stored of the union over J in A(I,:) of P(J,:), so with S_i the set of all such J,
-// C(i,:) = union over J in S_i of P(J,:).  One wavefront per row i builds S_i in an LDS table,
-// then C(i,:) in a second one: neighbouring fine rows I share most of their J, so each distinct
-// J is walked once instead of once per I.  A row whose S_i or C(i,:) outgrows its table is
-// flagged and listed in `ovf` (count pass) and left to the launches by capacity class; a table
-// is checked after every step of 64 inserts and holds at most (capacity - 65) keys before a
-// step, so probing always finds a free slot.  Count pass: cnt[i] = |C(i,:)|.  Fill pass: the
-// sorted columns at C_rowptr[i], for rows not flagged.
+// C(i,:) = union over J in S_i of P(J,:).  One wavefront per row i builds S_i in an LDS table
+// (each half-wavefront takes one I at a time, its lanes the entries of A(I,:)), then C(i,:) in a
+// second table (each lane one J of S_i): neighbouring fine rows I share most of their J, so each
+// distinct J is walked once instead of once per I.  A row whose S_i or C(i,:) outgrows its table
+// is flagged and listed in `ovf` (count pass) and left to the launches by capacity class.
+// Count pass: cnt[i] = |C(i,:)|.  Fill pass: the sorted columns at C_rowptr[i], for rows not
+// flagged.
 // =============================================================================================
 constexpr int kTwoSCap = 512, kTwoSMax = kTwoSCap - WAVE - 1;
 constexpr int kTwoCCap = 256, kTwoCMax = kTwoCCap - WAVE - 1;
 
 struct TwoLevelScratch {
-  int off[WAVE];
-  int st[WAVE];
   int skeys[kTwoSCap];
   int slist[kTwoSMax + 1];
   int ckeys[kTwoCCap];
   int clist[kTwoCMax + 1];
 };
 
-// Flattened walk over the entries of nl rows: row x of the list spans [start, start + len) of
-// `col` (row_of(x, start, len)); f(key) for each entry, 64 entries per step.  After each step
-// the count of new keys (ballot over the lanes' `fresh`) is added to *occ; the walk stops and
-// returns false as soon as *occ exceeds `limit`.
-template <class RowOf, class F>
-__device__ __forceinline__ bool walk_insert(int nl, RowOf row_of, const int* __restrict__ col, int* off,
-                                            int* st, int& occ, int limit, F&& insert) {
-  const int ln = lane();
-  for (int base = 0; base < nl; base += WAVE) {
-    int s = 0, l = 0;
-    if (base + ln < nl) row_of(base + ln, s, l);
-    const int incl = wave_incl_scan(l);
-    const int total = __shfl(incl, WAVE - 1, WAVE);
-    off[ln] = incl - l;
-    st[ln] = s;
-    wave_sync();
-    for (int q0 = 0; q0 < total; q0 += WAVE) {
-      const int q = q0 + ln;
-      bool fresh = false;
-      if (q < total) {
-        int lo = 0;
-#pragma unroll
-        for (int step = WAVE / 2; step > 0; step >>= 1)
-          if (off[lo + step] <= q) lo += step;
-        fresh = insert(col[st[lo] + (q - off[lo])]);
-      }
-      occ += __popcll(ballot(fresh));
-      if (occ > limit) {
-        wave_sync();
-        return false;
-      }
-    }
-    wave_sync();
-  }
-  return true;
-}
-
 template <bool FILL>
 __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int* __restrict__ pt_ptr,
                                                            const int* __restrict__ pt_row, int* cnt,
                                                            unsigned char* flag, int* ovf, int* novf,
-                                                           const int* __restrict__ C_rowptr, int* C_col) {
+                                                           const int* __restrict__ C_rowptr, int* C_col,
+                                                           int row0, int row1) {
   __shared__ TwoLevelScratch scr[kSymWaves];
   const int wid = threadIdx.x / WAVE, ln = lane();
-  const long long i64 = (long long)blockIdx.x * kSymWaves + wid;
-  if (i64 >= p.m) return;  // uniform over the wavefront
+  const int h = ln >> 5, sub = ln & 31;
+  const long long i64 = row0 + (long long)blockIdx.x * kSymWaves + wid;
+  if (i64 >= row1) return;  // uniform over the wavefront
   const int i = (int)i64;
   if (FILL && flag[i]) return;
   TwoLevelScratch& sc = scr[wid];
@@ -423,24 +412,49 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
   wave_sync();
   constexpr int sshift = 32 - 9, cshift = 32 - 8;
   static_assert(kTwoSCap == 512 && kTwoCCap == 256, "shifts assume these capacities");
-  // level 1: S_i from the rows of A under the fine rows I of column i of P
-  const int t0 = pt_ptr[i], t1 = pt_ptr[i + 1];
+  auto s_ins = [&](int key) {
+    bool fresh;
+    hs_insert<false>(sc.skeys, kTwoSCap - 1, sshift, key, fresh);
+    return fresh;
+  };
+  auto c_ins = [&](int key) {
+    bool fresh;
+    hs_insert<false>(sc.ckeys, kTwoCCap - 1, cshift, key, fresh);
+    return fresh;
+  };
+  // level 1: S_i from the rows of A under the fine rows I of column i of P, 64 of them at a time
+  const int t0 = pt_ptr[i], nI = pt_ptr[i + 1] - t0;
   int ns = 0;
-  bool ok = walk_insert(
-      t1 - t0,
-      [&](int x, int& s, int& l) {
-        const int I = pt_row[t0 + x];
-        s = p.A_rowptr[I];
-        l = p.A_rowptr[I + 1] - s;
-      },
-      p.A_col, sc.off, sc.st, ns, kTwoSMax,
-      [&](int key) {
-        bool fresh;
-        hs_insert<false>(sc.skeys, kTwoSCap - 1, sshift, key, fresh);
-        return fresh;
-      });
+  bool over = false;
+  for (int xb = 0; xb < nI; xb += WAVE) {
+    const int nb = min(WAVE, nI - xb);
+    int a0 = 0, al = 0;
+    if (ln < nb) {
+      const int I = pt_row[t0 + xb + ln];
+      a0 = p.A_rowptr[I];
+      al = p.A_rowptr[I + 1] - a0;
+    }
+    const int maxal = wave_max(al);
+    for (int x = 0; x < nb; x += 4) {  // two rows I per half-wavefront per round
+      const int xa = x + h, xc = x + 2 + h;
+      // (every lane takes part in the shuffles; the lengths of rows past the batch are zeroed after)
+      const int sa = __shfl(a0, xa & (WAVE - 1), WAVE), la_raw = __shfl(al, xa & (WAVE - 1), WAVE);
+      const int sb = __shfl(a0, xc & (WAVE - 1), WAVE), lb_raw = __shfl(al, xc & (WAVE - 1), WAVE);
+      const int la_ = xa < nb ? la_raw : 0, lb = xc < nb ? lb_raw : 0;
+      for (int e0 = 0; e0 < maxal; e0 += 32) {
+        const int ka = e0 + sub < la_ ? p.A_col[sa + e0 + sub] : -1;
+        const int kb = e0 + sub < lb ? p.A_col[sb + e0 + sub] : -1;
+        bool fresh = ka >= 0 && !over && s_ins(ka);
+        ns += __popcll(ballot(fresh));
+        over = over || ns > kTwoSMax;
+        fresh = kb >= 0 && !over && s_ins(kb);
+        ns += __popcll(ballot(fresh));
+        over = over || ns > kTwoSMax;
+      }
+    }
+  }
   int nc = 0;
-  if (ok) {
+  if (!over) {
     // S_i as a list
     int base = 0;
     for (int s0 = 0; s0 < kTwoSCap; s0 += WAVE) {
@@ -450,29 +464,25 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
       base += __popcll(mk);
     }
     wave_sync();
-    // level 2: C(i,:) from the rows of P under S_i
-    ok = walk_insert(
-        ns,
-        [&](int x, int& s, int& l) {
-          const int J = sc.slist[x];
-          s = p.P_rowptr[J];
-          l = p.P_rowptr[J + 1] - s;
-        },
-        p.P_col, sc.off, sc.st, nc, kTwoCMax,
-        [&](int key) {
-          bool fresh;
-          hs_insert<false>(sc.ckeys, kTwoCCap - 1, cshift, key, fresh);
-          return fresh;
-        });
+    // level 2: C(i,:) from the rows of P under S_i, one J per lane
+    for (int xb = 0; xb < ns && !over; xb += WAVE) {
+      int s = 0, l = 0;
+      if (xb + ln < ns) {
+        const int J = sc.slist[xb + ln];
+        s = p.P_rowptr[J];
+        l = p.P_rowptr[J + 1] - s;
+      }
+      insert_segments(s, l, p.P_col, ~0ULL, kTwoCMax, nc, over, c_ins);
+    }
   }
   if constexpr (!FILL) {
     if (ln == 0) {
-      cnt[i] = ok ? nc : 0;
-      flag[i] = ok ? 0 : 1;
-      if (!ok) ovf[atomicAdd(novf, 1)] = i;
+      cnt[i] = over ? 0 : nc;
+      flag[i] = over ? 1 : 0;
+      if (over) ovf[atomicAdd(novf, 1)] = i;
     }
   } else {
-    if (!ok) return;  // not reached for rows the count pass kept
+    if (over) return;  // not reached for rows the count pass kept
     int base = 0;
     for (int s0 = 0; s0 < kTwoCCap; s0 += WAVE) {
       const int k = sc.ckeys[s0 + ln];
@@ -493,15 +503,16 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
 
 hipError_t launch_c_two_level(const Patterns& p, const int* pt_ptr, const int* pt_row, bool fill, int* cnt,
                               unsigned char* flag, int* ovf, int* novf, const int* C_rowptr, int* C_col,
-                              hipStream_t s) {
-  if (p.m <= 0) return hipSuccess;
-  const dim3 grid(blocks_for(p.m, kSymWaves));
+                              int row0, int row1, hipStream_t s) {
+  if (row0 < 0 || row1 > p.m) return hipErrorInvalidValue;
+  if (row1 <= row0) return hipSuccess;
+  const dim3 grid(blocks_for((long long)row1 - row0, kSymWaves));
   if (fill)
     hipLaunchKernelGGL(k_c_two_level<true>, grid, dim3(kSymBlock), 0, s, p, pt_ptr, pt_row, cnt, flag, ovf, novf,
-                       C_rowptr, C_col);
+                       C_rowptr, C_col, row0, row1);
   else
     hipLaunchKernelGGL(k_c_two_level<false>, grid, dim3(kSymBlock), 0, s, p, pt_ptr, pt_row, cnt, flag, ovf,
-                       novf, C_rowptr, C_col);
+                       novf, C_rowptr, C_col, row0, row1);
   return hipGetLastError();
 }
 
@@ -582,6 +593,125 @@ hipError_t launch_rowform_codes(int mode, int nrows, const int* r, const int* x_
   if (nrows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rowform_codes, dim3(blocks_for(nrows, kSymBlock)), dim3(kSymBlock), 0, s, mode, nrows, r,
                      x_ptr, c_ptr, P_rowptr, P_col, short_ok ? 1 : 0, code);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Launch classes of the adjoint (dA = P dC P^T and dP = A P dC^T + A^T P dC, Section 3's products
+// read backwards): the table of fine row I holds U_I, the distinct columns of the rows of dC
+// (C's pattern) under P(I,:), which include R_I's.  Each half-wavefront counts U_I for one row in
+// a 128-slot LDS table, its lanes taking the entries of P(I,:); a row with more than
+// kAdjCountMax distinct columns takes min(walk, m) as its bound instead, walk being the number of
+// entries of those rows of C.  need = max(|U_I| or the bound, |R_I|, 1); rows whose P(I,:) has at
+// most kAdjMaxSegs entries, whose walk is at most kAdjMaxWalk and whose table fits `fast_cap`
+// slots get code 32 + log2(capacity) (the short-row kernel), the others log2(capacity); rows
+// with an empty P(I,:) get -1.
+// =============================================================================================
+constexpr int kAdjCountCap = 128;
+constexpr int kAdjCountMax = kAdjCountCap - 32 - 1;
+
+__global__ __launch_bounds__(kSymBlock) void k_adj_codes(Patterns p, const int* __restrict__ r,
+                                                         const int* __restrict__ C_rowptr,
+                                                         const int* __restrict__ C_col, int fast_cap, int* code) {
+  __shared__ int keys_all[2 * kSymWaves][kAdjCountCap];
+  const int wid = threadIdx.x / WAVE, ln = lane();
+  const int h = ln >> 5, sub = ln & 31;
+  const long long first = ((long long)blockIdx.x * kSymWaves + wid) * 2;
+  if (first >= p.n) return;  // uniform over the wavefront
+  const long long I64 = first + h;
+  const bool live = I64 < p.n;
+  const int I = live ? (int)I64 : 0;
+  int* keys = keys_all[2 * wid + h];
+  for (int q = sub; q < kAdjCountCap; q += 32) keys[q] = EMPTY;
+  wave_sync();
+  const unsigned long long group = h ? 0xFFFFFFFF00000000ULL : 0x00000000FFFFFFFFULL;
+  const int p0 = live ? p.P_rowptr[I] : 0, np = live ? p.P_rowptr[I + 1] - p0 : 0;
+  const int maxp = wave_max(np);
+  long long walk = 0;
+  int occ = 0;
+  bool over = false;
+  for (int eb = 0; eb < maxp; eb += 32) {
+    int s = 0, l = 0;
+    if (eb + sub < np) {
+      const int i = p.P_col[p0 + eb + sub];
+      s = C_rowptr[i];
+      l = C_rowptr[i + 1] - s;
+    }
+    walk += l;
+    insert_segments(s, l, C_col, group, kAdjCountMax, occ, over, [&](int key) {
+      bool fresh;
+      hs_insert<false>(keys, kAdjCountCap - 1, 32 - 7, key, fresh);
+      return fresh;
+    });
+  }
+#pragma unroll
+  for (int d = 16; d > 0; d >>= 1) walk += __shfl_xor(walk, d, WAVE);  // within the half
+  if (live && sub == 0) {
+    int out = -1;
+    if (np > 0) {
+      long long need = over ? (walk < p.m ? walk : p.m) : occ;
+      need = need > r[I] ? need : r[I];
+      need = need > 1 ? need : 1;
+      const int b = dev_cap_log2(need);
+      const bool fast = np <= kAdjMaxSegs && walk <= kAdjMaxWalk && (1LL << b) <= fast_cap;
+      out = fast ? 32 + b : b;
+    }
+    code[I] = out;
+  }
+}
+
+hipError_t launch_adj_codes(const Patterns& p, const int* r, const int* C_rowptr, const int* C_col, int fast_cap,
+                            int* code, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_codes, dim3(blocks_for(p.n, 2 * kSymWaves)), dim3(kSymBlock), 0, s, p, r, C_rowptr, C_col,
+                     fast_cap, code);
+  return hipGetLastError();
+}
+
+// =============================================================================================
+// Bounds that fix the owner tiles' size before |R_I| is known: out[0] = max over fine rows I with
+// a non-empty P(I,:) of min over i in P(I,:) of |C(i,:)| (R_I lies within every such C(i,:), so
+// this bounds |R_I| for every row the fold needs); out[1] = max over I of max(nnz(P(I,:)),
+// nnz(A(I,:))).  out zeroed by the caller.
+// =============================================================================================
+__global__ __launch_bounds__(kSymBlock) void k_row_bounds(Patterns p, const int* __restrict__ C_rowptr,
+                                                          unsigned* out) {
+  __shared__ int red[2][kSymWaves];
+  int rb = 0, lm = 0;
+  for (long long I = (long long)blockIdx.x * kSymBlock + threadIdx.x; I < p.n; I += (long long)gridDim.x * kSymBlock) {
+    const int pb = p.P_rowptr[I], pe = p.P_rowptr[I + 1];
+    if (pe > pb) {
+      int mn = INT32_MAX;
+      for (int e = pb; e < pe; ++e) {
+        const int i = p.P_col[e];
+        mn = min(mn, C_rowptr[i + 1] - C_rowptr[i]);
+      }
+      rb = max(rb, mn);
+    }
+    lm = max(lm, max(pe - pb, p.A_rowptr[I + 1] - p.A_rowptr[I]));
+  }
+  rb = wave_max(rb);
+  lm = wave_max(lm);
+  const int wid = threadIdx.x / WAVE;
+  if (lane() == 0) {
+    red[0][wid] = rb;
+    red[1][wid] = lm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kSymWaves; ++w) {
+      rb = max(rb, red[0][w]);
+      lm = max(lm, red[1][w]);
+    }
+    atomicMax(out, (unsigned)rb);
+    atomicMax(out + 1, (unsigned)lm);
+  }
+}
+
+hipError_t launch_row_bounds(const Patterns& p, const int* C_rowptr, unsigned* out, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_bounds, dim3(std::min(blocks_for(p.n, kSymBlock), 1024)), dim3(kSymBlock), 0, s, p,
+                     C_rowptr, out);
   return hipGetLastError();
 }
 
