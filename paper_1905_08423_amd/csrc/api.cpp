@@ -176,6 +176,8 @@ struct PinnedBuf {
   }
 };
 
+constexpr size_t kRowStoreMaxBytes = (size_t)512 << 20;  // largest row store of C's count pass
+
 // Device-to-host copy into page-locked memory, then wait.
 template <class T>
 void read_back(T* host, const T* dev, size_t count, hipStream_t s) {
@@ -571,6 +573,7 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   int* c_cnt = nullptr;
   unsigned char* c_flag = nullptr;
   int* c_ovf = nullptr;
+  int* c_store = nullptr;  // rows of C of at most kRowStore columns, sorted, from the count pass
   int n_c_ovf = 0;
   int rmax_all = 0, pmax_all = 0;
   // merged / all-at-once with tiles to grow: C's fill pass runs range by range in the owner branch,
@@ -616,12 +619,23 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     c_cnt = t.get<int>(m + 1);
     c_flag = t.get<unsigned char>(m);
     c_ovf = t.get<int>(m);
+    // (the store is skipped where it would pass kRowStoreMaxBytes: those rows take the fill pass)
+    if ((size_t)m * kRowStore * sizeof(int) <= kRowStoreMaxBytes) c_store = t.get<int>((size_t)m * kRowStore);
     hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, false, c_cnt, c_flag, c_ovf, dflag + 2,
-                             nullptr, nullptr, 0, m, s));
+                             nullptr, nullptr, c_store, dflag + 3, 0, m, s));
   }
   read_back(hsm, dflag, 4, s);
   if (hsm[0]) fail(PTAP_ERR_TOO_LARGE);
   n_c_ovf = hsm[2];
+  const int n_c_fill = hsm[3];  // rows of C longer than the row store holds
+  // C's columns for rows [lo, hi) once the row pointers are known: the fill pass for rows longer
+  // than the row store, a copy for the others
+  auto fill_c = [&](int lo, int hi) {
+    if (n_c_fill > 0)
+      hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr, P->C_rowptr,
+                               P->C_col, nullptr, nullptr, lo, hi, s));
+    if (c_store) hipck(launch_c_from_store(P->C_rowptr, c_store, c_flag, lo, hi, P->C_col, s));
+  };
   if (fill_by_range && n_c_ovf > 0) {
     // the rows of C the union left are sized by sum |R_I|: form R_I now
     launch_r();
@@ -723,12 +737,14 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         put_classes(t, cls);
         t.put(gtab);
       }
-      if (!fill_by_range)
-        hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
-                                 P->C_rowptr, P->C_col, 0, m, s));
+      if (!fill_by_range) fill_c(0, m);
     }
     t.put(c_cnt);
     t.put(c_ovf);
+    if (!fill_by_range) {
+      t.put(c_store);
+      c_store = nullptr;
+    }
     P->pattern_bytes = (int64_t)(m + 1 + acc) * (int64_t)sizeof(int);
   }
 
@@ -810,13 +826,16 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
     bool atomic = P->opt.fold == PTAP_FOLD_ATOMIC;
     if (!atomic) {
       // C's pattern on the host for growing the tiles (page-locked memory): the row pointers
-      // first, then the columns range by range, each range's tiles growing as soon as its
-      // columns have arrived
+      // first, then the columns (filled at once) copied range by range, each range's tiles
+      // growing as soon as its columns have arrived
       PinnedBuf cbuf(((size_t)m + 1 + (size_t)P->nnzC) * sizeof(int), s);
       int* h_c_ptr = cbuf.as<int>();
       int* h_c_col = h_c_ptr + m + 1;
       read_back(h_c_ptr, P->C_rowptr, (size_t)m + 1, s);
       const int nparts = grow_parts(m);
+      fill_c(0, m);
+      t.put(c_store);
+      c_store = nullptr;
       std::vector<hipEvent_t> arrived(nparts, nullptr);
       struct EventsGuard {
         std::vector<hipEvent_t>& e;
@@ -828,8 +847,6 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
       for (int q = 0; q < nparts; ++q) {
         int lo, hi;
         grow_range_bounds(m, nparts, q, lo, hi);
-        hipck(launch_c_two_level(pat, P->pt_ptr, P->pt_row, true, nullptr, c_flag, nullptr, nullptr,
-                                 P->C_rowptr, P->C_col, lo, hi, s));
         const size_t b = (size_t)h_c_ptr[lo], e = (size_t)h_c_ptr[hi];
         if (e > b)
           hipck(hipMemcpyAsync(h_c_col + b, P->C_col + b, (e - b) * sizeof(int), hipMemcpyDeviceToHost, s));

@@ -106,19 +106,21 @@ inline int cap_log2(long long need) {
 // device memory).  Rows within a tile are listed in ascending order.  Only state[lo..hi) is read
 // or written, so ranges can be grown at the same time.
 inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE, int TR, int* state,
-                std::vector<int>& tptr, std::vector<int>& trows, std::vector<char>& tglob) {
+                       std::vector<int>& tptr, std::vector<int>& trows, std::vector<char>& tglob) {
   // state: -1 free, -2 queued for the tile being grown, >= 0 taken
   std::vector<int> queue;
+  queue.reserve(4096);
   tptr.assign(1, 0);
   trows.clear();
   tglob.clear();
+  const unsigned span = (unsigned)(hi - lo);
+  int taken = 0;
   for (int seed = lo; seed < hi; ++seed) {
     if (state[seed] != -1) continue;
     const int T = (int)tglob.size();
     if (cptr[seed + 1] - cptr[seed] > TE) {
       state[seed] = T;
-      trows.push_back(seed);
-      tptr.push_back((int)trows.size());
+      tptr.push_back(++taken);
       tglob.push_back(1);
       continue;
     }
@@ -128,29 +130,37 @@ inline void grow_range(int lo, int hi, const int* cptr, const int* ccol, int TE,
     size_t head = 0;
     long long acc = 0;
     int nrows = 0;
+    // entries and rows queued beyond `head`: once taking every queued row would pass a limit,
+    // the tile is sure to stop within the queue, so rows taken from then on need not queue
+    // their neighbours (the tile comes out the same)
+    long long queued = cptr[seed + 1] - cptr[seed];
     while (head < queue.size()) {
       const int r = queue[head];
       const int sz = cptr[r + 1] - cptr[r];
       if (acc + sz > TE || nrows >= TR) break;
       ++head;
       acc += sz;
+      queued -= sz;
       ++nrows;
       state[r] = T;
-      trows.push_back(r);
+      if (acc + queued > TE || nrows + (long long)(queue.size() - head) > TR) continue;
       for (int k = cptr[r]; k < cptr[r + 1]; ++k) {
         const int c = ccol[k];
-        if (c >= lo && c < hi && state[c] == -1) {
+        if ((unsigned)(c - lo) < span && state[c] == -1) {
           state[c] = -2;
           queue.push_back(c);
+          queued += cptr[c + 1] - cptr[c];
         }
       }
     }
     for (size_t q = head; q < queue.size(); ++q) state[queue[q]] = -1;  // not taken
-    tptr.push_back((int)trows.size());
+    taken += nrows;
+    tptr.push_back(taken);
     tglob.push_back(0);
   }
   // list each tile's rows in ascending order: one pass over the range puts every row at the next
   // free position of its tile
+  trows.resize((size_t)taken);
   std::vector<int> pos(tptr.begin(), tptr.end() - 1);
   for (int i = lo; i < hi; ++i) trows[pos[state[i]]++] = i;
 }

@@ -114,11 +114,16 @@ hipError_t launch_validate_pattern(const int* rowptr, const int* col, int nrows,
 // |R_I| and min(w_I, m) of every fine row; rows whose product count could overflow the one-pass
 // table get r = 0 and are appended to ovf (*novf zeroed by the caller).
 hipError_t launch_ap_count(const Patterns& p, int* r, int* w, int* ovf, int* novf, hipStream_t s);
-// C's pattern by the two-level union over rows [row0, row1): count pass (cnt, flag, ovf / novf
-// for rows left to the class launches) or fill pass (rows not flagged).
+// C's pattern by the two-level union over rows [row0, row1): count pass (cnt; flag 1 and ovf /
+// novf for rows left to the class launches; flag 2 for rows written sorted to the row store,
+// kRowStore ints per row of C, when store is given; flag 0 and *nfill += 1 for the others) or
+// fill pass (rows of flag 0).  launch_c_from_store copies the stored rows into C_col.
+constexpr int kRowStore = 32;
 hipError_t launch_c_two_level(const Patterns& p, const int* pt_ptr, const int* pt_row, bool fill, int* cnt,
                               unsigned char* flag, int* ovf, int* novf, const int* C_rowptr, int* C_col,
-                              int row0, int row1, hipStream_t s);
+                              int* store, int* nfill, int row0, int row1, hipStream_t s);
+hipError_t launch_c_from_store(const int* C_rowptr, const int* store, const unsigned char* flag, int row0, int row1,
+                               int* C_col, hipStream_t s);
 hipError_t launch_c_bound_list(const int* pt_ptr, const int* pt_row, const int* r, const int* list, int count,
                                int m, long long* bound, hipStream_t s);
 hipError_t launch_tile_slot(const int* tptr, const int* trows, int ntiles, int* slot, hipStream_t s);

@@ -380,8 +380,11 @@ hipError_t launch_ap_count(const Patterns& p, int* r, int* w, int* ovf, int* nov
 // second table (each lane one J of S_i): neighbouring fine rows I share most of their J, so each
 // distinct J is walked once instead of once per I.  A row whose S_i or C(i,:) outgrows its table
 // is flagged and listed in `ovf` (count pass) and left to the launches by capacity class.
-// Count pass: cnt[i] = |C(i,:)|.  Fill pass: the sorted columns at C_rowptr[i], for rows not
-// flagged.
+// Count pass: cnt[i] = |C(i,:)|; a row of at most kRowStore columns goes, sorted, to its slot of
+// the row store (if one is given) and is copied into C_col once the row pointers are known, so
+// that only longer rows take the fill pass.  flag[i]: 0 fill pass, 1 class launches, 2 row
+// store; *nfill counts the rows of flag 0.  Fill pass: the sorted columns at C_rowptr[i], for
+// rows of flag 0.
 // =============================================================================================
 constexpr int kTwoSCap = 512, kTwoSMax = kTwoSCap - WAVE - 1;
 constexpr int kTwoCCap = 256, kTwoCMax = kTwoCCap - WAVE - 1;
@@ -398,14 +401,14 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
                                                            const int* __restrict__ pt_row, int* cnt,
                                                            unsigned char* flag, int* ovf, int* novf,
                                                            const int* __restrict__ C_rowptr, int* C_col,
-                                                           int row0, int row1) {
+                                                           int* store, int* nfill, int row0, int row1) {
   __shared__ TwoLevelScratch scr[kSymWaves];
   const int wid = threadIdx.x / WAVE, ln = lane();
   const int h = ln >> 5, sub = ln & 31;
   const long long i64 = row0 + (long long)blockIdx.x * kSymWaves + wid;
   if (i64 >= row1) return;  // uniform over the wavefront
   const int i = (int)i64;
-  if (FILL && flag[i]) return;
+  if (FILL && flag[i] != 0) return;
   TwoLevelScratch& sc = scr[wid];
   for (int q = ln; q < kTwoSCap; q += WAVE) sc.skeys[q] = EMPTY;
   for (int q = ln; q < kTwoCCap; q += WAVE) sc.ckeys[q] = EMPTY;
@@ -475,14 +478,8 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
       insert_segments(s, l, p.P_col, ~0ULL, kTwoCMax, nc, over, c_ins);
     }
   }
-  if constexpr (!FILL) {
-    if (ln == 0) {
-      cnt[i] = over ? 0 : nc;
-      flag[i] = over ? 1 : 0;
-      if (over) ovf[atomicAdd(novf, 1)] = i;
-    }
-  } else {
-    if (over) return;  // not reached for rows the count pass kept
+  // C(i,:)'s columns in ascending order at out
+  auto emit = [&](int* out) {
     int base = 0;
     for (int s0 = 0; s0 < kTwoCCap; s0 += WAVE) {
       const int k = sc.ckeys[s0 + ln];
@@ -491,28 +488,62 @@ __global__ __launch_bounds__(kSymBlock) void k_c_two_level(Patterns p, const int
       base += __popcll(mk);
     }
     wave_sync();
-    int* out = C_col + C_rowptr[i];
     for (int x = ln; x < base; x += WAVE) {
       const int key = sc.clist[x];
       int rank = 0;
       for (int y = 0; y < base; ++y) rank += sc.clist[y] < key;
       out[rank] = key;
     }
+  };
+  if constexpr (!FILL) {
+    const bool stored = !over && store && nc <= kRowStore;
+    if (stored) emit(store + (size_t)i * kRowStore);
+    if (ln == 0) {
+      cnt[i] = over ? 0 : nc;
+      flag[i] = over ? 1 : (stored ? 2 : 0);
+      if (over) ovf[atomicAdd(novf, 1)] = i;
+      if (!over && !stored) atomicAdd(nfill, 1);
+    }
+  } else {
+    if (over) return;  // not reached for rows the count pass kept
+    emit(C_col + C_rowptr[i]);
   }
+}
+
+// Rows the count pass kept in the row store, copied to their place in C_col: one thread per
+// (row, position), so reads and writes run along the rows.
+__global__ __launch_bounds__(kSymBlock) void k_c_from_store(const int* __restrict__ C_rowptr,
+                                                            const int* __restrict__ store,
+                                                            const unsigned char* __restrict__ flag, int row0,
+                                                            int row1, int* C_col) {
+  const long long t = (long long)blockIdx.x * kSymBlock + threadIdx.x;
+  const long long i = row0 + t / kRowStore;
+  const int e = (int)(t % kRowStore);
+  if (i >= row1 || flag[i] != 2) return;
+  const int b = C_rowptr[i];
+  if (e < C_rowptr[i + 1] - b) C_col[b + e] = store[(size_t)i * kRowStore + e];
+}
+
+hipError_t launch_c_from_store(const int* C_rowptr, const int* store, const unsigned char* flag, int row0, int row1,
+                               int* C_col, hipStream_t s) {
+  if (row1 <= row0) return hipSuccess;
+  hipLaunchKernelGGL(k_c_from_store, dim3(blocks_for(((long long)row1 - row0) * kRowStore, kSymBlock)),
+                     dim3(kSymBlock), 0, s, C_rowptr, store, flag, row0, row1, C_col);
+  return hipGetLastError();
 }
 
 hipError_t launch_c_two_level(const Patterns& p, const int* pt_ptr, const int* pt_row, bool fill, int* cnt,
                               unsigned char* flag, int* ovf, int* novf, const int* C_rowptr, int* C_col,
-                              int row0, int row1, hipStream_t s) {
+                              int* store, int* nfill, int row0, int row1, hipStream_t s) {
   if (row0 < 0 || row1 > p.m) return hipErrorInvalidValue;
   if (row1 <= row0) return hipSuccess;
   const dim3 grid(blocks_for((long long)row1 - row0, kSymWaves));
   if (fill)
     hipLaunchKernelGGL(k_c_two_level<true>, grid, dim3(kSymBlock), 0, s, p, pt_ptr, pt_row, cnt, flag, ovf, novf,
-                       C_rowptr, C_col, row0, row1);
+                       C_rowptr, C_col, store, nfill, row0, row1);
   else
     hipLaunchKernelGGL(k_c_two_level<false>, grid, dim3(kSymBlock), 0, s, p, pt_ptr, pt_row, cnt, flag, ovf,
-                       novf, C_rowptr, C_col, row0, row1);
+                       novf, C_rowptr, C_col, store, nfill, row0, row1);
   return hipGetLastError();
 }
 
