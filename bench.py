@@ -64,6 +64,50 @@ def profiled_traffic():
     return int(float(fields["traffic_bytes_per_launch"]))
 
 
+# Single-kernel runs for counter profiles: (workload, plan options, block size, adjoint)
+PROFILE_CASES = {
+    "c2_owner": ("c2", dict(algo="merged", fold="owner"), 1, False),
+    "c2_atomic": ("c2", dict(algo="merged", fold="atomic"), 1, False),
+    "c2_twostep": ("c2", dict(algo="twostep"), 1, False),
+    "c3b_owner": ("c3b", dict(algo="merged", fold="owner"), 1, False),
+    "c3b_atomic": ("c3b", dict(algo="merged", fold="atomic"), 1, False),
+    "c3b_twostep": ("c3b", dict(algo="twostep"), 1, False),
+    "c3c_bsr": ("c3c", dict(), 4, False),
+    "c3c_scalar_owner": ("c3c", dict(algo="merged", fold="owner"), 1, False),
+    "c5_adjoint": ("c5", dict(algo="merged", backward=True), 1, True),
+}
+
+
+def profile_case(lib, gen, torch, dev, name, steps, warmup):
+    wl, opts, bs, adjoint = PROFILE_CASES[name]
+    A, P, _ = gen.galerkin_workload(wl)
+    if bs > 1:
+        A, P = gen.csr_to_bsr(A, bs), gen.csr_to_bsr(P, bs)
+        n, m, Aval, Pval = A.nb, P.mb, A.val.reshape(-1), P.val.reshape(-1)
+    else:
+        n, m, Aval, Pval = A.n_rows, P.n_cols, A.val, P.val
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    plan = lib.Plan(n, m, d(A.rowptr, torch.int32), d(A.col, torch.int32), d(P.rowptr, torch.int32),
+                    d(P.col, torch.int32), block_size=bs, **opts)
+    Av, Pv = d(Aval, torch.float64), d(Pval, torch.float64)
+    C = plan.numeric(Av, Pv)
+    dC = torch.ones_like(C) if adjoint else None
+    step = (lambda: plan.backward(Av, Pv, dC)) if adjoint else (lambda: plan.numeric(Av, Pv, C))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    print(json.dumps({"profile_case": name, "ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
+                      "fold_used": st["fold_used"], "n_tiles": st["n_tiles"], "rows_formed": st["rows_formed"],
+                      "nnz_C": st["nnz_C"]}), flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +123,9 @@ def parse():
                     help="time only the two-step numeric on the workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of known size (counter calibration) and exit")
+    ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES),
+                    help="run one plan's numeric (or adjoint) --warmup + --steps times and exit: "
+                         "the workloads the counter summaries under profiles/ are taken on")
     ap.add_argument("--size-sweep", type=int, nargs="+", metavar="SIDE",
                     help="time the headline form (merged, owner fold, K = 1) on the 27-point "
                          "lognormal workload at each fine grid side, one JSON line per side, and exit")
@@ -108,6 +155,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}))
+        return
+
+    if args.profile_case:
+        profile_case(lib, gen, torch, dev, args.profile_case, args.steps, args.warmup)
         return
 
     if args.fwd_bwd_only:
@@ -172,7 +223,14 @@ def main():
                           "peak_extra_mb": round(extra / 2**20, 2)}))
         return
 
-    # ---------------- headline: merged (K = 1) owner fold
+    # ---------------- headline: merged (K = 1) owner fold.  The process's first plan also pays
+    # one-time costs (page-locked staging buffers, code object loading); it is timed and released
+    # first, so symbolic_ms is the time of a plan built after it.
+    torch.cuda.synchronize()
+    t_first = time.perf_counter()
+    lib.Plan(n, m, A_rowptr, A_col, P_rowptr, P_col, algo="merged", fold="owner").close()
+    torch.cuda.synchronize()
+    sym_first_ms = (time.perf_counter() - t_first) * 1e3
     plan, C, sym_ms, extra_aao = make_plan(algo="merged", fold="owner", nblocks=1)
     st = plan.stats()
     nnzC = st["nnz_C"]
@@ -207,6 +265,7 @@ def main():
                      "launch_ms_median": round(ev_median, 4), "launch_ms_min": round(ev_min, 4),
                      "measured_read_GBps": stream_read_gbps(lib, torch, dev)},
         "symbolic_ms": round(sym_ms, 2),
+        "symbolic_ms_first_plan_of_process": round(sym_first_ms, 2),
         "rows_formed_per_numeric": st["rows_formed"],
         "rows_needed": st["rows_needed"],
         "fold_terms": st["fold_terms"],

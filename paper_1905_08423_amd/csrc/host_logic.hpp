@@ -227,8 +227,8 @@ inline unsigned choose_hash_mul(int m, const int* cptr, const int* ccol) {
 // All rows of C in tiles: the rows are split into up to kGrowParts contiguous ranges of at least
 // kGrowPartRows rows, grown on threads of their own, and the ranges' tiles listed in range order.
 // The split depends on m only, so the tiles are the same on every machine.
-constexpr int kGrowParts = 16;
-constexpr int kGrowPartRows = 16384;
+constexpr int kGrowParts = 8;
+constexpr int kGrowPartRows = 32768;
 
 inline int grow_parts(int m) { return (int)std::max<long long>(1, std::min<long long>(kGrowParts, m / kGrowPartRows)); }
 

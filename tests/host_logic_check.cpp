@@ -154,17 +154,17 @@ int main() {
   std::printf("ok capacities\n");
 
   std::vector<int> ptr, col;
-  stencil27(40, ptr, col);  // 64,000 rows: three ranges
+  stencil27(40, ptr, col);  // 64,000 rows: one range
   check_tiles("27pt_40", 40 * 40 * 40, ptr, col, 3049, 1024);
   const unsigned golden = 0x9E3779B1u;
-  stencil27(64, ptr, col);  // 262,144 rows: sixteen ranges
+  stencil27(64, ptr, col);  // 262,144 rows: eight ranges
   check_tiles("27pt_64", 64 * 64 * 64, ptr, col, 3049, 1024);
   check_tiles("27pt_64_small_tiles", 64 * 64 * 64, ptr, col, 200, 16);
   const unsigned mul64 = choose_hash_mul(64 * 64 * 64, ptr.data(), col.data());
   if (mul64 != golden) fail("hash multiplier at 64^3 is not the golden ratio", mul64);
   std::printf("ok hash multiplier 64^3 keeps the golden ratio\n");
 
-  // a chain of 100,003 rows: six ranges of unequal size
+  // a chain of 100,003 rows: three ranges of unequal size
   {
     const int m = 100003;
     ptr.assign(m + 1, 0);

@@ -110,14 +110,14 @@ def test_c2_full_constant_coefficients_bit_exact():
     _check_full(g, ref, exact=True, algo="allatonce", fold="owner", nblocks=8)
 
 
-@pytest.mark.parametrize("side,ranges", [(93, 6), (121, 13)])
+@pytest.mark.parametrize("side,ranges", [(93, 3), (121, 6)])
 def test_owner_tiles_over_uneven_row_ranges(side, ranges):
-    """Coarse grids of 47^3 = 103,823 and 61^3 = 226,981 rows: the owner tiles are grown on 6 and
-    13 contiguous row ranges (one per 16,384 rows, at most 16) whose sizes differ by one row.  A
-    row left out of every tile, or held by two, would show as a wrong entry of C."""
+    """Coarse grids of 47^3 = 103,823 and 61^3 = 226,981 rows: the owner tiles are grown on 3 and
+    6 contiguous row ranges (one per 32,768 rows, at most 8) whose sizes differ by one row.  A row
+    left out of every tile, or held by two, would show as a wrong entry of C."""
     A, P = gen.stencil27(side, seed=5), gen.trilinear(side)
     m = P.n_cols
-    assert min(16, m // 16384) == ranges and m % ranges != 0
+    assert min(8, m // 32768) == ranges and m % ranges != 0
     ref = _oracle(A, P)
     g = GpuProblem(A, P)
     st = _check_full(g, ref)

@@ -33,5 +33,5 @@ def test_host_logic(driver):
                  "ok tiles random_long_rows", "ok hash multiplier 64^3", "ok hash multiplier 108^3",
                  "ok hash multiplier edge cases", "ok owner layout aligned", "ok fold estimate"]:
         assert any(l.startswith(want) for l in lines), (want, r.stdout)
-    # the chain of 100,003 rows is split into six unequal ranges
-    assert any("chain_100003 (100003 rows, 6 ranges" in l for l in lines), r.stdout
+    # the chain of 100,003 rows is split into three unequal ranges
+    assert any("chain_100003 (100003 rows, 3 ranges" in l for l in lines), r.stdout
