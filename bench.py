@@ -583,7 +583,7 @@ def batched(lib, gen, torch, dev):
     A, P = probs[big]
     tp, report = lib.tune(A.n_rows, P.n_cols, d(A.rowptr, torch.int32), d(A.col, torch.int32),
                           d(P.rowptr, torch.int32), d(P.col, torch.int32), d(A.val, torch.float64),
-                          d(P.val, torch.float64), candidates=lib.TUNE_CANDIDATES[:4], base={"algo": "merged"})
+                          d(P.val, torch.float64), candidates=lib.TUNE_CANDIDATES, base={"algo": "merged"})
     tuned = tp.tuned_options
     tp.close()
     plans, Av, Pv, keep = [], [], [], []

@@ -124,7 +124,12 @@ typedef struct ptap_options {
                             (Eq. allatoncerow).  The halo lists cost 4 bytes per halo row per
                             tile, held by the plan (ptap_stats.workspace_bytes); tiles whose halo
                             does not fit in LDS use the other kernels. */
-  int32_t reserved[4];
+  uint32_t hash_mul;     /* owner fold, short-row kernel: the odd multiplier of its R_I hash (slot =
+                            top 6 bits of key * hash_mul).  0: chosen at symbolic time from a
+                            sample of C's rows (the golden ratio unless a fixed candidate needs
+                            far fewer probes).  Any odd value gives the same C; an even value is
+                            PTAP_ERR_INPUT. */
+  int32_t reserved[3];
 } ptap_options;
 
 typedef struct ptap_stats {
@@ -149,6 +154,8 @@ typedef struct ptap_stats {
   int64_t tile_entries;        /* owner fold: entries of C a tile holds at most (0: no tiles) */
   double est_owner_ms;         /* PTAP_FOLD_AUTO: the fold cost model's estimate of the numeric */
   double est_atomic_ms;        /* time with the owner and with the atomic fold (0 otherwise) */
+  int64_t hash_mul;            /* owner fold: the short-row kernel's R_I hash multiplier in use
+                                  (ptap_options.hash_mul, or the one symbolic chose); 0 without tiles */
 } ptap_stats;
 
 typedef struct ptap_plan ptap_plan;

@@ -45,7 +45,8 @@ class ptap_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("backward", ctypes.c_int32), ("owner_waves", ctypes.c_int32),
                 ("tile_lds", ctypes.c_int32), ("cache", ctypes.c_int32),
-                ("owner_kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("owner_kernel", ctypes.c_int32), ("hash_mul", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class ptap_stats(ctypes.Structure):
@@ -58,7 +59,8 @@ class ptap_stats(ctypes.Structure):
                 ("cache_bytes", ctypes.c_int64), ("block_size", ctypes.c_int64),
                 ("staged_tiles", ctypes.c_int64), ("staged_lds_bytes", ctypes.c_int64),
                 ("table_slots", ctypes.c_int64), ("tile_entries", ctypes.c_int64),
-                ("est_owner_ms", ctypes.c_double), ("est_atomic_ms", ctypes.c_double)]
+                ("est_owner_ms", ctypes.c_double), ("est_atomic_ms", ctypes.c_double),
+                ("hash_mul", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -301,7 +303,7 @@ class Plan:
     def __init__(self, n, m, A_rowptr, A_col, P_rowptr, P_col, *, algo="merged", fold="auto",
                  nblocks=1, tile_entries=0, hash_slots=0, validate=True, xcd_remap=True,
                  backward=False, owner_waves=0, tile_lds=0, cache=False, staged=False, block_size=1,
-                 allocator=None, stream=None):
+                 hash_mul=0, allocator=None, stream=None):
         load_library()
         self.n, self.m = int(n), int(m)
         self.A_rowptr, self.A_col = A_rowptr, A_col
@@ -321,6 +323,7 @@ class Plan:
         o.tile_lds = int(tile_lds)
         o.cache = 1 if cache else 0
         o.owner_kernel = 1 if staged else 0
+        o.hash_mul = int(hash_mul)
         self.options = o
         self.handle = None
         self.bs = int(block_size)
@@ -425,11 +428,20 @@ class Batch:
 
 # Option sets tried by tune(): workgroup size and tile budget of the owner fold (the LDS "bins"
 # the tiles are sized for), the atomic fold, and the numeric cache.
+# Option sets tune() tries: workgroup size (wavefronts), tile budget (LDS bytes and entries), the
+# short-row kernel's hash multiplier (the golden ratio forced; by default symbolic may pick another),
+# the largest on-chip table of the general kernels, the numeric cache and the fold.  The short-row
+# kernel's own table (64 slots, a fine row per 32 lanes) is fixed by its design.
+GOLDEN_HASH_MUL = 0x9E3779B1
 TUNE_CANDIDATES = (
     {},
     {"owner_waves": 8},
     {"tile_lds": 98304},
     {"tile_lds": 65536},
+    {"owner_waves": 4},
+    {"tile_entries": 2048},
+    {"hash_mul": GOLDEN_HASH_MUL},
+    {"hash_slots": 256},
     {"cache": True},
     {"fold": "atomic"},
 )

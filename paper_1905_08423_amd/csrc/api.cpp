@@ -455,6 +455,7 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
   if (o.fold < PTAP_FOLD_AUTO || o.fold > PTAP_FOLD_OWNER) return PTAP_ERR_INPUT;
   if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0 || o.tile_lds < 0) return PTAP_ERR_INPUT;
   if (o.owner_kernel < 0 || o.owner_kernel > 1) return PTAP_ERR_INPUT;
+  if (o.hash_mul != 0 && (o.hash_mul & 1u) == 0) return PTAP_ERR_INPUT;
   if (o.owner_waves != 0 && o.owner_waves != 4 && o.owner_waves != 8 && o.owner_waves != 16)
     return PTAP_ERR_INPUT;
   if (o.hash_slots && (o.hash_slots < 64 || (o.hash_slots & (o.hash_slots - 1)))) return PTAP_ERR_INPUT;
@@ -567,9 +568,11 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
 
   // --- |R_I| and w_I for every fine row (Alg. 1 / 2) in one pass; rows whose products could
   // outgrow its table go to launches by capacity class, sized by w_I.
-  int* r = t.get<int>(n);
-  int* w = t.get<int>(n);
-  int* ap_ovf = t.get<int>(n);
+  // |R_I|, w_I and the rows the one-pass table cannot hold; allocated when R_I is formed (after
+  // C's row store is released where R_I comes late), so the two are never held together
+  int* r = nullptr;
+  int* w = nullptr;
+  int* ap_ovf = nullptr;
   int* c_cnt = nullptr;
   unsigned char* c_flag = nullptr;
   int* c_ovf = nullptr;
@@ -584,7 +587,12 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   // products), reduced on the device once |R_I| is known; read back into hsm[8..17].
   unsigned long long* st = t.get<unsigned long long>(5);
   hipck(launch_fill_i32(reinterpret_cast<int*>(st), 0, 10, s));
-  auto launch_r = [&] { hipck(launch_ap_count(pat, r, w, ap_ovf, dflag + 1, s)); };
+  auto launch_r = [&] {
+    r = t.get<int>(n);
+    w = t.get<int>(n);
+    ap_ovf = t.get<int>(n);
+    hipck(launch_ap_count(pat, r, w, ap_ovf, dflag + 1, s));
+  };
   // after a read of dflag: rows the one-pass table could not hold, then the statistics
   auto finish_r = [&](int novf) {
     if (novf > 0) {
@@ -923,10 +931,14 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
           mul_err = std::current_exception();
         }
       };
-      try {
-        mul_thread = std::thread(pick_mul);
-      } catch (...) {
-        pick_mul();  // no thread to spare
+      if (P->opt.hash_mul) {
+        P->hash_mul = P->opt.hash_mul;
+      } else {
+        try {
+          mul_thread = std::thread(pick_mul);
+        } catch (...) {
+          pick_mul();  // no thread to spare
+        }
       }
       struct Joiner {
         std::thread& th;
@@ -1442,6 +1454,7 @@ ptap_status ptap_plan_stats(const ptap_plan* P, ptap_stats* out) {
   out->tile_entries = P->ntiles ? P->TE : 0;
   out->est_owner_ms = P->est_owner_ms;
   out->est_atomic_ms = P->est_atomic_ms;
+  out->hash_mul = P->ntiles > 0 ? (int64_t)P->hash_mul : 0;
   return PTAP_OK;
 }
 

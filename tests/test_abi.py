@@ -53,6 +53,19 @@ def test_counts_beyond_int32_rejected_without_gpu():
     assert L.ptap_copy_pattern(None, None, None, None) == lib.PTAP_ERR_INPUT
 
 
+def test_bad_options_rejected_without_gpu():
+    """Option values out of range are PTAP_ERR_INPUT before any device call: an even hash
+    multiplier, an unknown owner kernel, a workgroup size other than 4, 8 or 16."""
+    fake = ctypes.c_void_p(0x1000)
+    L = lib.load_library()
+    for field, value in [("hash_mul", 2), ("hash_mul", 0x9E3779B0), ("owner_kernel", 2), ("owner_waves", 12)]:
+        o = lib.ptap_options_default()
+        setattr(o, field, value)
+        h = ctypes.c_void_p()
+        st = L.ptap_plan_create(ctypes.byref(h), 10, 4, fake, fake, 10, fake, fake, 10, ctypes.byref(o), None, None)
+        assert st == lib.PTAP_ERR_INPUT and not h.value, (field, value, st)
+
+
 gpu = pytest.mark.gpu
 
 

@@ -180,3 +180,25 @@ def test_numeric_cache(case):
     plain = g.plan(algo="merged", fold="owner")
     assert plain.stats()["cache_bytes"] == 0
     plain.close()
+
+
+
+def test_forced_hash_multiplier_same_product():
+    """ptap_options.hash_mul: any odd multiplier of the short-row kernel's R_I hash gives the same
+    C (bit-exact on dyadic C1; under the value criterion on a lognormal operator), and the stats
+    report the multiplier in use."""
+    from gpu_util import GpuProblem
+    from helpers import assert_close
+    for A, P, exact in [(gen.laplacian7(16), gen.trilinear(16), True),
+                        (gen.stencil27(20, seed=3), gen.trilinear(20), False)]:
+        g = GpuProblem(A, P)
+        ref = oracle.ptap(A, P)
+        for mul in (0x9E3779B1, 0x00000001, 0x7FFFFFFF, 0xDEADBEEF):
+            plan = g.plan(fold="owner", hash_mul=mul)
+            assert plan.stats()["hash_mul"] == mul
+            C = plan.numeric(g.A_val, g.P_val).cpu().numpy()
+            if exact:
+                assert np.array_equal(C, ref.val)
+            else:
+                assert_close(C, ref.val, ref.abs)
+            plan.close()
