@@ -529,15 +529,12 @@ def block_workload(lib, gen, torch, dev):
     return res
 
 
-def batched(lib, gen, torch, dev):
-    """The batched form against plain per-plan launches: (i) a 6-level geometric hierarchy from a
-    256^3 7-point Laplacian (trilinear P at every level, each level's A the previous C), one
-    persistent launch per level in one HIP graph; (ii) 64 independent 27-point lognormal problems
-    with grid sides uniform in 12..64 (seed 3), one persistent launch."""
+def hierarchy_case(lib, gen, torch, dev, top, nlev):
+    """Geometric hierarchy from a top^3 7-point Laplacian (trilinear P at every level, each level's
+    A the previous C): the plain per-level numerics against the batch (one level after another in
+    one HIP graph)."""
     d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
-    res = {}
-    # (i) hierarchy
-    sides = gen.hierarchy_sides(256, 6)
+    sides = gen.hierarchy_sides(top, nlev)
     A0 = gen.laplacian7(sides[0])
     A_rowptr, A_col = d(A0.rowptr, torch.int32), d(A0.col, torch.int32)
     A0_val = d(A0.val, torch.float64)
@@ -564,14 +561,26 @@ def batched(lib, gen, torch, dev):
     t_plain = _time_events(plain_h, 10, torch)
     t_batch = _time_events(lambda: batch.numeric(A_vals, Pv, C), 10, torch)
     diff = max(float(((c - cp).abs().max() / cp.abs().max().clamp_min(1e-300)).item()) for c, cp in zip(C, Cp))
-    res["hierarchy_256cubed_6_levels"] = {"products": len(plans), "plain_ms": round(t_plain, 4),
-                                          "batched_graph_ms": round(t_batch, 4),
-                                          "max_rel_diff_vs_plain": diff}
+    out = {"sides": [int(x) for x in sides], "products": len(plans), "plain_ms": round(t_plain, 4),
+           "batched_graph_ms": round(t_batch, 4), "max_rel_diff_vs_plain": diff}
     batch.close()
     for p in plans:
         p.close()
     del C, Cp, A_vals, A_plain, keep, Pv
     torch.cuda.empty_cache()
+    return out
+
+
+def batched(lib, gen, torch, dev):
+    """The batched form against plain per-plan launches: (i) geometric hierarchies (hierarchy_case),
+    one level after another in one HIP graph; (ii) 64 independent 27-point lognormal problems
+    with grid sides uniform in 12..64 (seed 3), one persistent launch."""
+    d = lambda a, t: torch.as_tensor(np.ascontiguousarray(a), dtype=t).to(dev)  # noqa: E731
+    res = {}
+    # (i) hierarchies: 256^3 down in 6 levels (large levels), 64^3 down to 2^3 (small levels,
+    # where launch overhead counts)
+    for top, nlev in ((256, 6), (64, 6)):
+        res[f"hierarchy_{top}cubed_{nlev}_levels"] = hierarchy_case(lib, gen, torch, dev, top, nlev)
     # (ii) independent problems; plan options tuned by measurement on the largest of them
     sides3 = gen.batch_problem_sides(64, seed=3, lo=12, hi=64)
     probs = []

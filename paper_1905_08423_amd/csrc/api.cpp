@@ -1554,6 +1554,10 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       ptap_plan* P = b->plans[k];
       const NumericArgs& a = desc[k].a;
       if (err == hipSuccess && P->any_tile_global) err = launch_fill_f64(b->C_vals[k], 0.0, P->nnzC, b->cap);
+      // one plan at this level, or A's values past 2 GiB: the plan's own launch (its grid, tiles
+      // mapped to XCDs in order).  The persistent work-list kernel was slower for single-plan
+      // levels: 9.07 against 7.00 ms on the 256^3 six-level hierarchy, 0.47 against 0.24 ms on
+      // 64^3 down to 2^3 (its 512 workgroups per level mostly find no work on small levels).
       const bool single = b->level_plans[l].size() == 1 || P->wide_a;
       if (P->fold_used == PTAP_FOLD_ATOMIC) {  // the atomic fold: the plan's own launches
         if (err == hipSuccess) {
@@ -1575,12 +1579,13 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
         if (!c.fast)
           err = launch_owner_numeric(a, c, ts, P->tile_fptr, P->tile_fine, P->TE,
                                      P->opt.xcd_remap != 0, P->gtab, P->gval, b->cap);
-        else if (single)  // one plan at this level: its own grid, tiles mapped to XCDs in order
+        else if (single)
           err = launch_owner_fast(a, c, ts, P->tile_fptr, P->tile_fine, P->TE, P->owner_waves,
                                   P->opt.xcd_remap != 0, b->cap);
       }
     }
-    if (err == hipSuccess && b->level_plans[l].size() > 1)
+    // the short-row tiles of a level's several plans in one persistent launch
+    if (err == hipSuccess && b->level_plans[l].size() > 1 && b->nitems[l] > 0)
       err = launch_owner_fast_batch(b->d_plans, b->items[l], b->nitems[l], b->counters + l * kXcds,
                                     b->grid, b->lds, b->cap);
   }
