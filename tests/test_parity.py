@@ -202,3 +202,51 @@ def test_forced_hash_multiplier_same_product():
             else:
                 assert_close(C, ref.val, ref.abs)
             plan.close()
+
+
+
+def _mixed_long_short(seed):
+    """Fine rows n = 3000, coarse m = 400: a banded A (7 entries a row) with every 1500th row dense
+    (600 random columns), and a P whose rows mostly take one to three nearby coarse columns while
+    every 700th row takes 30 random ones.  Most rows stay short; the long ones outgrow the
+    symbolic phase's one-pass tables (|R_I| beyond 31 keys, C(i,:) beyond 191 columns, the fine
+    rows S_i reached through A beyond 447), so the class launches that take over run beside the
+    one-pass kernels in one plan."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n, m = 3000, 400
+    rows, cols = [], []
+    for i in range(n):
+        c = set(range(max(0, i - 3), min(n, i + 4)))
+        if i % 1500 == 0:
+            c |= set(rng.choice(n, size=600, replace=False).tolist())
+        rows += [i] * len(c)
+        cols += sorted(c)
+    A = sp.csr_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, n))
+    rows, cols = [], []
+    for I in range(n):
+        base = I * m // n
+        c = set(range(base, min(m, base + 1 + I % 3)))
+        if I % 700 == 0:
+            c |= set(rng.choice(m, size=30, replace=False).tolist())
+        rows += [I] * len(c)
+        cols += sorted(c)
+    P = sp.csr_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, m))
+    return gen.from_scipy(A), gen.from_scipy(P)
+
+
+@pytest.mark.parametrize("algo,fold,K", [("merged", "owner", 1), ("allatonce", "owner", 3),
+                                         ("merged", "atomic", 1), ("twostep", "auto", 1),
+                                         ("merged", "auto", 1)])
+def test_symbolic_fallback_rows(algo, fold, K):
+    import scipy.sparse as sp
+    A, P = _mixed_long_short(seed=11)
+    # the input reaches every path: rows of C within the row store (<= 32), longer rows within the
+    # one-pass table (<= 191), rows beyond it, S_i beyond 447 and R_I beyond 31 keys
+    Ab = sp.csr_matrix((np.ones(A.nnz), A.col, A.rowptr), shape=(A.n_rows, A.n_rows))
+    Pb = sp.csr_matrix((np.ones(P.nnz), P.col, P.rowptr), shape=(P.n_rows, P.n_cols))
+    c_len = np.diff((Pb.T @ Ab @ Pb).tocsr().indptr)
+    assert (c_len <= 32).any() and ((c_len > 32) & (c_len <= 191)).any() and (c_len > 191).any()
+    assert np.diff((Pb.T @ Ab).tocsr().indptr).max() > 447
+    assert np.diff((Ab @ Pb).tocsr().indptr).max() > 31
+    check_against_oracle(A, P, algo=algo, fold=fold, nblocks=K)
