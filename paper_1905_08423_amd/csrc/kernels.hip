@@ -388,7 +388,7 @@ hipError_t launch_c_rows(const Patterns& p, const int* pt_ptr, const int* pt_row
 // rows in ascending order.
 // =============================================================================================
 constexpr int kTileBlock = 256;
-constexpr int kWindowBits = 32768;
+constexpr int kWindowBits = 262144;  // 32 KiB of LDS: one window covers a 128^3 tile's candidates
 
 __device__ __forceinline__ int block_reduce_min(int v, int* red) {
   v = -wave_max(-v);
