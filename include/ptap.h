@@ -200,9 +200,13 @@ ptap_status ptap_plan_create_bsr(ptap_plan** out, int32_t nb, int32_t mb, int32_
 /*
  * Symbolic phase (Section 2; Alg. 7/9 for all-at-once and merged, Alg. 5 for two-step):
  * computes and keeps the pattern of C and every index structure the numeric phase needs.
- * Synchronises the stream (it reads nnz(C) and the row classes on the host).  For the owner
- * fold it groups C's rows into tiles on the host with up to 8 threads of its own (joined before
- * it returns); the tiles depend on the patterns only, not on the machine.
+ * Runs on the device and synchronises the stream: the host reads back counters (nnz(C), the
+ * sizes of the row classes built on the device) and, for the owner fold, C's pattern, from
+ * which it groups C's rows into tiles with up to 8 threads of its own (one more chooses the hash
+ * multiplier; all joined before it returns); the tiles depend on the patterns only, not on the
+ * machine.  Host copies go through page-locked buffers that the library allocates itself and
+ * keeps in a process-wide pool for later plans (buffers above 256 MiB are freed after use).
+ * Temporary device memory comes from the plan's allocator and is released before it returns.
  * Errors: PTAP_ERR_STATE if already done, PTAP_ERR_TOO_LARGE, PTAP_ERR_OOM, PTAP_ERR_HIP.
  */
 ptap_status ptap_symbolic(ptap_plan* plan, hipStream_t stream);
