@@ -1086,11 +1086,17 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
         if (!fast && !tg && owner_general_lds_bytes(TE, cap, cap > lmax, false) > (size_t)P->lds_device)
           tg = 1;
         if (tg && tptr[k + 1] - tptr[k] != 1) fail(PTAP_ERR_UNSUPPORTED);  // a device-memory tile holds one row
-        groups[std::make_tuple(fast ? 1 : 0, fast ? 0 : cap, tg)].push_back(k);
+        // short-row tiles with a row of C of more than 64 columns fold those rows key by key
+        int long_c = 0;
+        if (fast)
+          for (int q = tptr[k]; q < tptr[k + 1] && !long_c; ++q)
+            long_c = h_c_ptr[trows[q] + 1] - h_c_ptr[trows[q]] > 2 * kHalfLanes ? 1 : 0;
+        groups[std::make_tuple(fast ? 1 : 0, fast ? long_c : cap, tg)].push_back(k);
       }
       for (auto& kv : groups) {
         TileClass tc;
         tc.fast = std::get<0>(kv.first) != 0;
+        tc.long_c = tc.fast && std::get<1>(kv.first) != 0;
         tc.cap = tc.fast ? 64 : std::get<1>(kv.first);
         tc.hash_global = !tc.fast && tc.cap > lmax;
         tc.tile_global = std::get<2>(kv.first) != 0;

@@ -37,6 +37,7 @@ struct TileClass {
   bool hash_global = false;
   bool tile_global = false;
   bool fast = false;     // short-row kernel (owner.hip)
+  bool long_c = false;   // short-row kernel: some row of C in these tiles has more than 64 columns
   int count = 0;
   int* tiles = nullptr;  // device, tile ids
   std::vector<int> host_tiles;

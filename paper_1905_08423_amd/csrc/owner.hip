@@ -119,7 +119,9 @@ __device__ __forceinline__ Stage4 st_pext(const Stage3& q, const Gather& g) {
 
 // One tile of the owner fold by the whole workgroup (NW wavefronts); smem holds the tile and the
 // per-wavefront hash tables.  Ends with the tile written to C and a workgroup barrier.
-template <int NW, bool PEXT, bool WIDE>
+// LONGC: the tile has rows of C longer than 2 * kHalf columns (R_I has at most 32 keys); an
+// owned entry whose row of C is that long is folded key by key (see the fold).
+template <int NW, bool PEXT, bool WIDE, bool LONGC>
 __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, const TileSet& ts,
                                                 const int* __restrict__ tile_fptr,
                                                 const int* __restrict__ tile_fine, int TE,
@@ -240,10 +242,33 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
         for (int kk = 0; kk < nmax; ++kk) {
           const SegRec rc = hs->rec[half][kk];
           const int c0 = kk < nsel ? rc.base : 0, c1 = kk < nsel ? rc.pad : 0;
-          for (int c = c0 + sub; c < c1; c += kHalf) {
-            const int j = tc[c];
-            const int s = hash_find64(keys, j, hmul);
-            if (s >= 0) atomicAdd(tv + c, rc.w * vals[s]);
+          if (LONGC && c1 - c0 > 2 * kHalf) {
+            // A row of C much longer than R_I: walking it would look up mostly columns that R_I
+            // lacks.  Instead each lane takes the keys in its two slots of the table and finds
+            // their positions in the row (its columns are sorted) by binary search; every key of
+            // R_I is a column of C(i,:) (C's pattern is the structural product).
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+              const int sidx = sub + h2 * kHalf;
+              const int j = keys[sidx];
+              if (j != EMPTY) {
+                int lo = c0, hi = c1;
+                while (lo < hi) {
+                  const int mid = (lo + hi) >> 1;
+                  if (tc[mid] < j)
+                    lo = mid + 1;
+                  else
+                    hi = mid;
+                }
+                if (lo < c1 && tc[lo] == j) atomicAdd(tv + lo, rc.w * vals[sidx]);
+              }
+            }
+          } else {
+            for (int c = c0 + sub; c < c1; c += kHalf) {
+              const int j = tc[c];
+              const int s = hash_find64(keys, j, hmul);
+              if (s >= 0) atomicAdd(tv + c, rc.w * vals[s]);
+            }
           }
         }
       }
@@ -264,7 +289,7 @@ __device__ __forceinline__ void owner_fast_tile(const NumericArgs& a, int tile, 
   __syncthreads();
 }
 
-template <int NW, bool PEXT, bool WIDE>
+template <int NW, bool PEXT, bool WIDE, bool LONGC>
 __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, const int* __restrict__ tiles,
                                                              TileSet ts,
                                                              const int* __restrict__ tile_fptr,
@@ -278,7 +303,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast(NumericArgs a, cons
     const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
     b = x * q + min(x, rem) + k;
   }
-  owner_fast_tile<NW, PEXT, WIDE>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
+  owner_fast_tile<NW, PEXT, WIDE, LONGC>(a, tiles[b], ts, tile_fptr, tile_fine, TE, smem);
 }
 
 // Batched form: a persistent grid works through a list of (plan, tile) items, every item one tile
@@ -309,7 +334,7 @@ __global__ __launch_bounds__(NW * WAVE, 8) void k_owner_fast_batch(const OwnerBa
       const int pk = __builtin_amdgcn_readfirstlane(w.x);
       const int tl = __builtin_amdgcn_readfirstlane(w.y);
       const OwnerBatchPlan& pl = plans[pk];
-      owner_fast_tile<NW, false, false>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
+      owner_fast_tile<NW, false, false, false>(pl.a, tl, pl.ts, pl.tile_fptr, pl.tile_fine, pl.TE, smem);
     }
   }
 }
@@ -318,19 +343,29 @@ size_t owner_fast_lds_bytes(int TE, int nw) {
   return (((size_t)TE * 12 + ((size_t)kTileRows + 1) * 4 + 15) / 16) * 16 + (size_t)nw * sizeof(HalfScratch);
 }
 
-template <bool PEXT, bool WIDE>
+template <bool PEXT, bool WIDE, bool LONGC>
 static void launch_fast_nw(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
                            const int* tile_fptr, const int* tile_fine, int TE, int nw, int remap,
                            size_t lds, hipStream_t s) {
   if (nw == 16)
-    hipLaunchKernelGGL((k_owner_fast<16, PEXT, WIDE>), dim3(tc.count), dim3(16 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
+    hipLaunchKernelGGL((k_owner_fast<16, PEXT, WIDE, LONGC>), dim3(tc.count), dim3(16 * WAVE), lds, s, a,
+                       tc.tiles, ts, tile_fptr, tile_fine, TE, remap);
   else if (nw == 8)
-    hipLaunchKernelGGL((k_owner_fast<8, PEXT, WIDE>), dim3(tc.count), dim3(8 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
+    hipLaunchKernelGGL((k_owner_fast<8, PEXT, WIDE, LONGC>), dim3(tc.count), dim3(8 * WAVE), lds, s, a,
+                       tc.tiles, ts, tile_fptr, tile_fine, TE, remap);
   else
-    hipLaunchKernelGGL((k_owner_fast<4, PEXT, WIDE>), dim3(tc.count), dim3(4 * WAVE), lds, s, a, tc.tiles,
-                       ts, tile_fptr, tile_fine, TE, remap);
+    hipLaunchKernelGGL((k_owner_fast<4, PEXT, WIDE, LONGC>), dim3(tc.count), dim3(4 * WAVE), lds, s, a,
+                       tc.tiles, ts, tile_fptr, tile_fine, TE, remap);
+}
+
+template <bool PEXT, bool WIDE>
+static void launch_fast_longc(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
+                              const int* tile_fptr, const int* tile_fine, int TE, int nw, int remap,
+                              size_t lds, hipStream_t s) {
+  if (tc.long_c)
+    launch_fast_nw<PEXT, WIDE, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+  else
+    launch_fast_nw<PEXT, WIDE, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
 }
 
 hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const TileSet& ts,
@@ -340,13 +375,13 @@ hipError_t launch_owner_fast(const NumericArgs& a, const TileClass& tc, const Ti
   const size_t lds = owner_fast_lds_bytes(TE, nw);
   const int remap = xcd_remap ? 1 : 0;
   if (a.A_pext && a.wide_a)
-    launch_fast_nw<true, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+    launch_fast_longc<true, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   else if (a.A_pext)
-    launch_fast_nw<true, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+    launch_fast_longc<true, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   else if (a.wide_a)
-    launch_fast_nw<false, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+    launch_fast_longc<false, true>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   else
-    launch_fast_nw<false, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
+    launch_fast_longc<false, false>(a, tc, ts, tile_fptr, tile_fine, TE, nw, remap, lds, s);
   return hipGetLastError();
 }
 
