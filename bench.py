@@ -41,7 +41,7 @@ PROFILE = os.path.join(ROOT, "profiles", "owner_numeric_128cubed_27pt.md")
 KERNEL_SOURCES = ["paper_1905_08423_amd/csrc/owner.hip", "paper_1905_08423_amd/csrc/short_rows.hpp",
                   "paper_1905_08423_amd/csrc/device.hpp", "paper_1905_08423_amd/csrc/internal.hpp",
                   "paper_1905_08423_amd/csrc/kernels.hip", "paper_1905_08423_amd/csrc/api.cpp",
-                  "paper_1905_08423_amd/csrc/host_logic.hpp"]
+                  "paper_1905_08423_amd/csrc/host_logic.hpp", "paper_1905_08423_amd/csrc/symbolic.hip"]
 
 
 def profiled_traffic():
