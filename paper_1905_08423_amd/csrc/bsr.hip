@@ -14,10 +14,13 @@
 // Blocks are read one entry per lane (the wavefront's load is contiguous); a lane takes the
 // other entries of its column from the lanes holding them (ds_bpermute), which costs the
 // address unit a quarter of loading the column in every lane.
+// 4 x 4 blocks take k_bsr_flat4 instead, which forms the blocks U of up to 32 entries of A(I,:)
+// first and then deals the row's block products out 32 at a time (see there).
 // The C pattern is the structural block product computed by the scalar symbolic phase on the
 // block patterns.  Summation order varies between runs (LDS and device atomics).
 #include "device.hpp"
 #include "internal.hpp"
+#include "short_rows.hpp"
 
 namespace ptapk {
 
@@ -89,9 +92,25 @@ __device__ __forceinline__ StepLoad step_load(const BsrArgs& a, int t0, int a1, 
 
 // LDS layout of the row kernel: keys[cap] (int), pos[cap] (int), then (LDS accumulation only)
 // acc[ncmax * bs^2] (double, 16-byte aligned).
-size_t bsr_lds_bytes(int bs, int cap, int ncmax, bool lds_acc) {
+// The 4 x 4 kernel adds one FlatScratch per wavefront after them.
+namespace {
+constexpr int kFlatSeg = 32;    // entries of A(I,:) whose blocks U are staged at a time
+constexpr int kFlatRounds = 8;  // rounds of 4 block products whose loads are issued together
+constexpr int kFlatWin = 4 * kFlatRounds;  // products dealt per batch
+static_assert(kFlatWin <= 32, "a batch's products are numbered by the lanes of one half");
+struct FlatScratch {
+  double urot[kFlatSeg][16];  // U = P(I,i)^T A(I,J) of each staged entry, row r rotated (below)
+  int2 rec[kFlatSeg];         // nonempty segments of the walk by rank: (offset into P, entry)
+};
+__host__ __device__ inline size_t bsr_head_bytes(int bs, int cap, int ncmax, bool lds_acc) {
   const size_t head = (((size_t)cap * 8) + 15) / 16 * 16;
   return lds_acc ? head + (size_t)ncmax * bs * bs * sizeof(double) : head;
+}
+}  // namespace
+
+size_t bsr_lds_bytes(int bs, int cap, int ncmax, bool lds_acc) {
+  const size_t head = (bsr_head_bytes(bs, cap, ncmax, lds_acc) + 15) / 16 * 16;
+  return bs == 4 ? head + kBsrWaves * sizeof(FlatScratch) : head;
 }
 
 template <int BS, bool LDS_ACC>
@@ -139,8 +158,6 @@ __global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_numeric(BsrArgs a, con
     double T[BS];  // lane (r, c): row r of P(I,i)^T, i.e. column r of P(I,i)
 #pragma unroll
     for (int k = 0; k < BS; ++k) T[k] = a.P_val[pIi + k * BS + r];
-    double Tr[4] = {0.0, 0.0, 0.0, 0.0};
-    if constexpr (BS == 4) rot_coef4(T, r, Tr);
     const int a0 = a.A_rowptr[I], a1 = a.A_rowptr[I + 1];
     // step loads (the entry A(I,J) of this lane's group, the extent of row J of P) are issued
     // one step ahead; the products of a step issue their loads kU at a time
@@ -150,20 +167,10 @@ __global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_numeric(BsrArgs a, con
       if (t0 + G < a1) nx = step_load<B2, G>(a, t0 + G, a1, g, ent, in_group);
       double U = 0.0;
       double Ur[BS];  // row r of this group's U
-      double Urr[4] = {0.0, 0.0, 0.0, 0.0};
-      if constexpr (BS == 4) {
-        U = col_dot4(Tr, cu.own);
-        Ur[0] = dpp_dbl<0x00>(U);
-        Ur[1] = dpp_dbl<0x55>(U);
-        Ur[2] = dpp_dbl<0xAA>(U);
-        Ur[3] = dpp_dbl<0xFF>(U);
-        rot_coef4(Ur, r, Urr);
-      } else {
 #pragma unroll
-        for (int k = 0; k < BS; ++k) U += T[k] * lane_dbl(cu.own, in_group ? g * B2 + k * BS + c : ln);
+      for (int k = 0; k < BS; ++k) U += T[k] * lane_dbl(cu.own, in_group ? g * B2 + k * BS + c : ln);
 #pragma unroll
-        for (int k = 0; k < BS; ++k) Ur[k] = lane_dbl(U, in_group ? g * B2 + r * BS + k : ln);
-      }
+      for (int k = 0; k < BS; ++k) Ur[k] = lane_dbl(U, in_group ? g * B2 + r * BS + k : ln);
       const int len = cu.pe - cu.ps;
       const int lmax = wave_max(len);
       for (int u0 = 0; u0 < lmax; u0 += kU) {
@@ -180,12 +187,8 @@ __global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_numeric(BsrArgs a, con
         for (int v = 0; v < kU; ++v) {
           if (u0 + v >= lmax) break;
           double V = 0.0;
-          if constexpr (BS == 4) {
-            V = col_dot4(Urr, pown[v]);
-          } else {
 #pragma unroll
-            for (int k = 0; k < BS; ++k) V += Ur[k] * lane_dbl(pown[v], in_group ? g * B2 + k * BS + c : ln);
-          }
+          for (int k = 0; k < BS; ++k) V += Ur[k] * lane_dbl(pown[v], in_group ? g * B2 + k * BS + c : ln);
           const int j = jj[v];
           if (j >= 0) {
             if (LDS_ACC) {
@@ -208,6 +211,148 @@ __global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_numeric(BsrArgs a, con
   }
 }
 
+
+// 4 x 4 blocks by a flattened walk.  The products of row I are the pairs (entry J of A(I,:),
+// block P(J,j)); taken entry by entry, every round of four products waits for its loads of P
+// before it can start.  Here a wavefront first forms U_J = P(I,i)^T A(I,J) for up to kFlatSeg
+// entries of A(I,:) (group g of 16 lanes takes entries g, g+4, ...; lane (r, c) holds U_J[r][c])
+// and leaves them in LDS, then deals the products of those entries out 32 at a time (a prefix
+// sum of the lengths of the rows of P gives every product its entry and its block of P), so the
+// loads of 32 block products are in flight together.  Lane (r, c) of the group that takes a
+// product P(J,j) adds sum_k U_J[r][k] P(J,j)[k][c] into block j of row i of C.  U_J is stored
+// with row r rotated, urot[J][4r + d] = U_J[r][(r - d) mod 4], which is the order in which
+// col_dot4 takes the coefficients, so a lane reads its four with two 16-byte LDS loads.
+template <bool LDS_ACC>
+__global__ __launch_bounds__(kBsrWaves * WAVE) void k_bsr_flat4(BsrArgs a, const int* __restrict__ rows,
+                                                                int nrows, int cap, int ncmax, int xcd_remap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* keys = reinterpret_cast<int*>(smem);
+  int* pos = keys + cap;
+  double* acc = reinterpret_cast<double*>(smem + (((size_t)cap * 8) + 15) / 16 * 16);
+  const int ln = lane(), wid = threadIdx.x / WAVE;
+  FlatScratch* fs = reinterpret_cast<FlatScratch*>(
+                        smem + (bsr_head_bytes(4, cap, ncmax, LDS_ACC) + 15) / 16 * 16) + wid;
+  const int g = ln >> 4, ent = ln & 15, r = ent >> 2, c = ent & 3;
+  const int q32 = ln & 31;
+  const unsigned shift = 32u - (unsigned)__builtin_ctz((unsigned)cap);
+
+  int b = blockIdx.x;
+  if (xcd_remap) {
+    const int T = gridDim.x, q = T / 8, rem = T % 8, x = b % 8, k = b / 8;
+    b = x * q + min(x, rem) + k;
+  }
+  if (b >= nrows) return;
+  const int i = rows[b];
+  const int c0 = a.C_rowptr[i], nc = a.C_rowptr[i + 1] - c0;
+
+  if (LDS_ACC) {
+    for (int s = threadIdx.x; s < cap; s += blockDim.x) keys[s] = EMPTY;
+    for (int x = threadIdx.x; x < nc * 16; x += blockDim.x) acc[x] = 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+      const int j = a.C_col[c0 + q];
+      unsigned s = hslot(j, (int)shift);
+      for (int it = 0; it < cap && atomicCAS(keys + s, EMPTY, j) != EMPTY; ++it) s = (s + 1) & (unsigned)(cap - 1);
+      pos[s] = q;
+    }
+    __syncthreads();
+  }
+
+  for (int qq = a.pt_ptr[i] + wid; qq < a.pt_ptr[i + 1]; qq += kBsrWaves) {
+    const int I = a.pt_row[qq];
+    const size_t pIi = (size_t)a.pt_pos[qq] * 16;
+    double T[4];  // lane (r, c): column r of P(I,i), i.e. row r of P(I,i)^T
+#pragma unroll
+    for (int k = 0; k < 4; ++k) T[k] = a.P_val[pIi + k * 4 + r];
+    double Tr[4];
+    rot_coef4(T, r, Tr);
+    const int a0 = a.A_rowptr[I], a1 = a.A_rowptr[I + 1];
+    for (int ch = a0; ch < a1; ch += kFlatSeg) {
+      const int ne = min(kFlatSeg, a1 - ch);
+      // lane q < ne of the lower half: entry ch + q and the extent of its row of P
+      int ps = 0, len = 0;
+      if (ln < ne) {
+        const int J = a.A_col[ch + ln];
+        ps = a.P_rowptr[J];
+        len = a.P_rowptr[J + 1] - ps;
+      }
+      double own[kFlatSeg / 4];
+#pragma unroll
+      for (int s = 0; s < kFlatSeg / 4; ++s) {
+        const int q = 4 * s + g;
+        own[s] = q < ne ? a.A_val[(size_t)(ch + q) * 16 + ent] : 0.0;
+      }
+      const int incl = half_incl_scan(len);  // upper half: len 0
+      const int tot = __builtin_amdgcn_readlane(incl, 31);
+      const unsigned long long nonempty = ballot(len > 0);
+      if (len > 0) fs->rec[prefix_count(nonempty)] = make_int2(ps - (incl - len), ln);
+#pragma unroll
+      for (int s = 0; s < kFlatSeg / 4; ++s) {
+        if (4 * s < ne) {  // uniform: every lane takes part in the row rotations
+          const double U = col_dot4(Tr, own[s]);
+          if (4 * s + g < ne) fs->urot[4 * s + g][4 * r + ((r - c) & 3)] = U;
+        }
+      }
+      wave_sync();
+      int before = 0;  // nonempty segments that end before the current window
+      for (int b0 = 0; b0 < tot; b0 += kFlatWin) {
+        // lane p < kFlatWin (of each half): product b0 + p, its segment by rank and its block of
+        // P; the window's segment ends are counted only up to kFlatWin, so `before` stays the
+        // rank of the segment that holds product b0 of the next batch
+        const int d = incl - b0 - 1;
+        const int bit = (len > 0 && (unsigned)d < (unsigned)kFlatWin) ? (int)(1u << d) : 0;
+        const unsigned ends = (unsigned)__builtin_amdgcn_readlane(half_or_scan(bit), 31);
+        const int rk = (before + __popc(ends & ((1u << q32) - 1u))) & (kFlatSeg - 1);
+        const int2 rc = fs->rec[rk];
+        // positions past the batch or the chunk's products deal nothing: their rank may name a
+        // record not written for this chunk, so neither its offset nor its entry is used
+        const int e_p = q32 < kFlatWin && b0 + q32 < tot ? b0 + q32 + rc.x : -1;
+        const int t_p = e_p >= 0 ? rc.y : 0;
+        before += __popc(ends);
+        // round u: group g takes product 4u + g
+        int eu[kFlatRounds], tu[kFlatRounds], jj[kFlatRounds];
+        double pv[kFlatRounds];
+#pragma unroll
+        for (int u = 0; u < kFlatRounds; ++u) {
+          eu[u] = __builtin_amdgcn_ds_bpermute((4 * u + g) * 4, e_p);
+          tu[u] = __builtin_amdgcn_ds_bpermute((4 * u + g) * 4, t_p);
+        }
+#pragma unroll
+        for (int u = 0; u < kFlatRounds; ++u) {
+          pv[u] = eu[u] >= 0 ? a.P_val[(size_t)eu[u] * 16 + ent] : 0.0;
+          jj[u] = eu[u] >= 0 ? a.P_col[eu[u]] : -1;
+        }
+        const int nr = min(kFlatRounds, (tot - b0 + 3) / 4);
+#pragma unroll
+        for (int u = 0; u < kFlatRounds; ++u) {
+          if (u < nr) {  // uniform
+            const double2* ur = reinterpret_cast<const double2*>(&fs->urot[tu[u]][4 * r]);
+            const double2 u01 = ur[0], u23 = ur[1];
+            const double w[4] = {u01.x, u01.y, u23.x, u23.y};
+            const double V = col_dot4(w, pv[u]);
+            const int j = jj[u];
+            if (j >= 0) {
+              if (LDS_ACC) {
+                unsigned s = hslot(j, (int)shift);
+                for (int it = 1; keys[s] != j && it < cap; ++it) s = (s + 1) & (unsigned)(cap - 1);
+                if (keys[s] == j) atomicAdd(acc + (size_t)pos[s] * 16 + ent, V);
+              } else {
+                const int p = row_find(a.C_col, c0, nc, j);
+                atomicAdd(a.C_val + ((size_t)c0 + p) * 16 + ent, V);
+              }
+            }
+          }
+        }
+      }
+      wave_sync();  // the staged blocks and records are rewritten by the next chunk
+    }
+  }
+  if (LDS_ACC) {
+    __syncthreads();
+    for (int x = threadIdx.x; x < nc * 16; x += blockDim.x) a.C_val[(size_t)c0 * 16 + x] = acc[x];
+  }
+}
+
 template <int BS>
 static void launch_bs(const BsrArgs& a, const int* rows, int nrows, int cap, int ncmax, bool lds_acc,
                       bool remap, hipStream_t s) {
@@ -227,7 +372,16 @@ hipError_t launch_bsr_numeric(const BsrArgs& a, int bs, const int* rows, int nro
     case 1: launch_bs<1>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
     case 2: launch_bs<2>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
     case 3: launch_bs<3>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
-    case 4: launch_bs<4>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
+    case 4: {
+      const size_t lds = bsr_lds_bytes(4, cap, ncmax, lds_acc);
+      if (lds_acc)
+        hipLaunchKernelGGL(k_bsr_flat4<true>, dim3(nrows), dim3(kBsrWaves * WAVE), lds, s, a, rows, nrows, cap,
+                           ncmax, remap ? 1 : 0);
+      else
+        hipLaunchKernelGGL(k_bsr_flat4<false>, dim3(nrows), dim3(kBsrWaves * WAVE), lds, s, a, rows, nrows, cap,
+                           ncmax, remap ? 1 : 0);
+      break;
+    }
     case 5: launch_bs<5>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
     case 6: launch_bs<6>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;
     case 7: launch_bs<7>(a, rows, nrows, cap, ncmax, lds_acc, remap, s); break;

@@ -105,6 +105,19 @@ def test_long_rows_accumulate_in_device_memory():
 
 
 @gpu
+@pytest.mark.parametrize("nb,mb,da,dp,seed", [(100, 30, 0.5, 0.2, 11), (60, 380, 0.6, 0.15, 12)])
+def test_block4_long_rows(nb, mb, da, dp, seed):
+    """4x4 blocks with rows of A longer than the 32 entries whose blocks the 4x4 kernel stages
+    at a time (several chunks per fine row); the second case also has rows of C longer than the
+    LDS accumulator, which take the device-atomic path."""
+    _need_gpu()
+    A = gen.random_bsr(nb, nb, 4, da, seed=seed, empty_rows=0.05)
+    P = gen.random_bsr(nb, mb, 4, dp, seed=50 + seed, empty_rows=0.05)
+    assert np.diff(A.rowptr).max() > 32
+    _check_bsr(A, P)
+
+
+@gpu
 def test_block_plan_errors_and_repeat():
     _need_gpu()
     import paper_1905_08423_amd as lib
