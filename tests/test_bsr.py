@@ -118,6 +118,27 @@ def test_block4_long_rows(nb, mb, da, dp, seed):
 
 
 @gpu
+def test_block4_chunk_and_batch_boundaries():
+    """4x4 blocks, rows of A with exactly 0, 1, 31, 32, 33, 64 and 65 blocks (the 4x4 kernel
+    stages 32 entries of A(I,:) at a time) and rows of P that are empty or up to 12 blocks long,
+    so that segments of the product walk are empty, end exactly at a 32-product batch or cross
+    one."""
+    _need_gpu()
+    rng = np.random.default_rng(77)
+    nb, mb = 140, 24
+    lens = np.array([0, 1, 31, 32, 33, 64, 65])[np.arange(nb) % 7]
+    rowptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([np.sort(rng.choice(nb, size=k, replace=False)) for k in lens]).astype(np.int64)
+    A = gen.BSR(nb, nb, 4, rowptr, col, rng.uniform(-1.0, 1.0, size=(len(col), 4, 4)))
+    plens = rng.integers(0, 13, size=nb)
+    plens[rng.random(nb) < 0.2] = 0
+    prow = np.concatenate([[0], np.cumsum(plens)]).astype(np.int64)
+    pcol = np.concatenate([np.sort(rng.choice(mb, size=k, replace=False)) for k in plens]).astype(np.int64)
+    P = gen.BSR(nb, mb, 4, prow, pcol, rng.uniform(-1.0, 1.0, size=(len(pcol), 4, 4)))
+    _check_bsr(A, P)
+
+
+@gpu
 def test_block_plan_errors_and_repeat():
     _need_gpu()
     import paper_1905_08423_amd as lib
