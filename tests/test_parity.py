@@ -32,6 +32,16 @@ def test_c1_bit_exact(algo, fold, K):
     check_against_oracle(A, P, exact=True, algo=algo, fold=fold, nblocks=K)
 
 
+@pytest.mark.parametrize("fold", ["owner", "atomic"])
+@pytest.mark.parametrize("K", [5000, 600000])
+def test_two_pass_more_blocks_than_rows(fold, K):
+    """All-at-once with more ownership blocks than fine rows (most entries of P off-block): the
+    block index takes 32-bit arithmetic at K = 5000 (n K < 2^31) and 64-bit at K = 600000."""
+    A, P, _ = gen.galerkin_workload("c1")
+    assert A.n_rows * 5000 < 2**31 <= A.n_rows * 600000
+    check_against_oracle(A, P, exact=True, algo="allatonce", fold=fold, nblocks=K)
+
+
 @pytest.mark.parametrize("algo,fold", ALGO_FOLD)
 def test_toy_rowwise(algo, fold):
     A, P = gen.toy_rowwise(seed=4)
