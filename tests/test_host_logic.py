@@ -1,7 +1,7 @@
 """CPU checks of the library's host logic for the symbolic phase (no GPU): table capacities, the
 owner tiles grown over contiguous row ranges, and the choice of the short-row kernel's hash
 multiplier.  The functions live in paper_1905_08423_amd/csrc/host_logic.hpp, which the library
-includes; tests/host_logic_check.cpp drives them and is built here with g++."""
+includes; tests/host_logic_check.cpp exercises them and is built here with g++."""
 import os
 import shutil
 import subprocess
@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.fixture(scope="module")
-def driver(tmp_path_factory):
+def host_logic_exe(tmp_path_factory):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
@@ -24,8 +24,8 @@ def driver(tmp_path_factory):
     return exe
 
 
-def test_host_logic(driver):
-    r = subprocess.run([driver], capture_output=True, text=True, timeout=300)
+def test_host_logic(host_logic_exe):
+    r = subprocess.run([host_logic_exe], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     lines = r.stdout.splitlines()
     assert not any(l.startswith("FAIL") for l in lines), r.stdout
