@@ -1555,7 +1555,11 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
   hipck(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
   hipError_t err = hipSuccess;
   for (size_t l = 0; l < b->levels.size() && err == hipSuccess; ++l) {
-    err = launch_fill_i32(b->counters + l * kXcds, 0, kXcds, b->cap);
+    // the work counters of the level's persistent launch; levels of one plan have none (on the
+    // 64^3 hierarchy the graph took 4.5% longer than plain launches with a fill at every level,
+    // 1.1% without)
+    const bool persistent = b->level_plans[l].size() > 1 && b->nitems[l] > 0;
+    if (persistent) err = launch_fill_i32(b->counters + l * kXcds, 0, kXcds, b->cap);
     for (int k : b->level_plans[l]) {
       ptap_plan* P = b->plans[k];
       const NumericArgs& a = desc[k].a;
@@ -1591,7 +1595,7 @@ static void batch_record(ptap_batch* b, hipStream_t s) {
       }
     }
     // the short-row tiles of a level's several plans in one persistent launch
-    if (err == hipSuccess && b->level_plans[l].size() > 1 && b->nitems[l] > 0)
+    if (err == hipSuccess && persistent)
       err = launch_owner_fast_batch(b->d_plans, b->items[l], b->nitems[l], b->counters + l * kXcds,
                                     b->grid, b->lds, b->cap);
   }
