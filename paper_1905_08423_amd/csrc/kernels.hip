@@ -519,11 +519,16 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict
   __shared__ int rows_l[kOrderMax];
   __shared__ unsigned char key_l[kOrderMax];
   __shared__ int hist[kOrderKeys];
-  __shared__ int red[kTileBlock / WAVE];
+  __shared__ int woff[kOrderKeys];                  // where each key's rows start in the window
+  __shared__ int wcnt[kTileBlock / WAVE][kOrderKeys];  // rows per key of each wavefront's lanes
+  static_assert(kOrderKeys == WAVE, "the key offsets are scanned by one wavefront");
+  static_assert(kTileBlock / WAVE * kOrderKeys == kTileBlock, "one count cleared per thread");
   const int tile = tiles[blockIdx.x];
   const int f0 = fptr[tile], nf = fptr[tile + 1] - f0;
   if (nf < 2 || nf > kOrderMax) return;
+  const int wv = threadIdx.x / WAVE;
   if (threadIdx.x < kOrderKeys) hist[threadIdx.x] = 0;
+  (&wcnt[0][0])[threadIdx.x] = 0;
   __syncthreads();
   for (int q = threadIdx.x; q < nf; q += kTileBlock) {
     const int I = fine[f0 + q];
@@ -542,19 +547,52 @@ __global__ __launch_bounds__(kTileBlock) void k_tile_order(const int* __restrict
   int nbins = 0;
   for (int v = 0; v < kOrderKeys; ++v) nbins += hist[v] > 0 ? 1 : 0;
   const int win = nbins <= kOrderFewKeys ? kTileBlock : nf;
+  // A stable counting sort of each window by key: the window's rows of key v follow those of
+  // smaller keys, in list order.  Per chunk of kTileBlock rows, a lane's rank among the earlier
+  // lanes of its wavefront with the same key comes from one ballot per distinct key, and the
+  // counts of the wavefronts before it from LDS.
   for (int w0 = 0; w0 < nf; w0 += win) {
     const int w1 = min(w0 + win, nf);
-    int written = 0;
-    for (int v = 0; v < kOrderKeys; ++v) {
-      if (hist[v] == 0) continue;  // the same for every thread
-      for (int base = w0; base < w1; base += kTileBlock) {
-        const int q = base + threadIdx.x;
-        const bool take = q < w1 && key_l[q] == v;
-        int total;
-        const int pos = block_excl_scan(take ? 1 : 0, red, total);
-        if (take) fine[f0 + w0 + written + pos] = rows_l[q];
-        written += total;
+    if (threadIdx.x < kOrderKeys) woff[threadIdx.x] = 0;
+    __syncthreads();
+    for (int q = w0 + threadIdx.x; q < w1; q += kTileBlock) atomicAdd(woff + key_l[q], 1);
+    __syncthreads();
+    if (wv == 0) {
+      const int c = woff[threadIdx.x];
+      const int incl = wave_incl_scan(c);
+      woff[threadIdx.x] = incl - c;
+    }
+    __syncthreads();
+    for (int base = w0; base < w1; base += kTileBlock) {
+      const int q = base + threadIdx.x;
+      const bool has = q < w1;
+      const int k = has ? key_l[q] : -1;
+      unsigned long long left = ballot(has);
+      int rank = 0;
+      while (left) {  // the same for every lane of the wavefront
+        const int leader = __builtin_ctzll(left);
+        const int kv = __shfl(k, leader, WAVE);
+        const unsigned long long m = ballot(has && k == kv);
+        if (has && k == kv) rank = prefix_count(m);
+        if (lane() == leader) wcnt[wv][kv] = __popcll(m);
+        left &= ~m;
       }
+      __syncthreads();
+      if (has) {
+        int pos = woff[k] + rank;
+        for (int w = 0; w < wv; ++w) pos += wcnt[w][k];
+        fine[f0 + w0 + pos] = rows_l[q];
+      }
+      __syncthreads();
+      if (threadIdx.x < kOrderKeys) {  // past this chunk's rows; counts cleared for the next
+        int add = 0;
+        for (int w = 0; w < kTileBlock / WAVE; ++w) {
+          add += wcnt[w][threadIdx.x];
+          wcnt[w][threadIdx.x] = 0;
+        }
+        woff[threadIdx.x] += add;
+      }
+      __syncthreads();
     }
   }
 }
