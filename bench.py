@@ -126,6 +126,9 @@ def parse():
     ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES),
                     help="run one plan's numeric (or adjoint) --warmup + --steps times and exit: "
                          "the workloads the counter summaries under profiles/ are taken on")
+    ap.add_argument("--symbolic-only", action="store_true",
+                    help="build the headline plan (merged, owner fold, K = 1) --warmup + --steps times "
+                         "with no numeric (for profiler runs of the symbolic phase) and exit")
     ap.add_argument("--size-sweep", type=int, nargs="+", metavar="SIDE",
                     help="time the headline form (merged, owner fold, K = 1) on the 27-point "
                          "lognormal workload at each fine grid side, one JSON line per side, and exit")
@@ -215,6 +218,20 @@ def main():
         per = [e0.elapsed_time(e1) for e0, e1 in evs]
         time_numeric.median = float(np.median(per))
         return wall_ms, float(np.mean(per)), float(np.min(per))
+
+    if args.symbolic_only:
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p_sym = lib.Plan(n, m, A_rowptr, A_col, P_rowptr, P_col, algo="merged", fold="owner")
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append((time.perf_counter() - t0) * 1e3)
+            p_sym.close()
+        print(json.dumps({"symbolic_only": True, "plans": len(times), "symbolic_ms_median": round(float(np.median(times)), 3),
+                          "symbolic_ms": [round(x, 3) for x in times]}), flush=True)
+        return
 
     if args.twostep_only:
         plan, C, sym_ms, extra = make_plan(algo="twostep")

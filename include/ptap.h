@@ -101,7 +101,11 @@ typedef struct ptap_options {
   int32_t hash_slots;    /* 0: automatic.  Otherwise the largest on-chip hash table, in slots
                             (power of two >= 64); longer rows use tables in device memory.
                             Setting it low forces the spill path (used by tests). */
-  int32_t validate;      /* nonzero: check both CSR inputs at plan creation (one sync) */
+  int32_t validate;      /* 1 (default): check both CSR inputs at plan creation and again at
+                            the start of ptap_symbolic (the caller's arrays may have changed in
+                            between); 2: at plan creation only, for callers that run the
+                            symbolic phase right after creating the plan; 0: never.  Each
+                            check is one pass over both patterns and one sync. */
   int32_t xcd_remap;     /* nonzero: map workgroups to tiles so that consecutive tiles run on
                             the same XCD (shared L2 for their common fine rows) */
   int32_t backward;      /* nonzero: also prepare the adjoint (ptap_backward) at symbolic time */

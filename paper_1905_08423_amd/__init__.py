@@ -316,7 +316,8 @@ class Plan:
         o.nblocks = int(nblocks)
         o.tile_entries = int(tile_entries)
         o.hash_slots = int(hash_slots)
-        o.validate = 1 if validate else 0
+        # the plan's symbolic phase follows right below, so the check at creation covers it
+        o.validate = 2 if validate else 0
         o.xcd_remap = 1 if xcd_remap else 0
         o.backward = 1 if backward else 0
         o.owner_waves = int(owner_waves)

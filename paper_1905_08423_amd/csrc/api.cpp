@@ -455,6 +455,7 @@ ptap_status ptap_plan_create(ptap_plan** out, int32_t n, int32_t m, const int32_
   if (o.fold < PTAP_FOLD_AUTO || o.fold > PTAP_FOLD_OWNER) return PTAP_ERR_INPUT;
   if (o.nblocks < 1 || o.tile_entries < 0 || o.hash_slots < 0 || o.tile_lds < 0) return PTAP_ERR_INPUT;
   if (o.owner_kernel < 0 || o.owner_kernel > 1) return PTAP_ERR_INPUT;
+  if (o.validate < 0 || o.validate > 2) return PTAP_ERR_INPUT;
   if (o.hash_mul != 0 && (o.hash_mul & 1u) == 0) return PTAP_ERR_INPUT;
   if (o.owner_waves != 0 && o.owner_waves != 4 && o.owner_waves != 8 && o.owner_waves != 16)
     return PTAP_ERR_INPUT;
@@ -535,9 +536,10 @@ static void symbolic_impl(ptap_plan* P, hipStream_t s) {
   const int n = pat.n, m = pat.m;
   const bool two = P->opt.algo == PTAP_TWOSTEP;
   const bool blk = P->bs > 1;
-  // The patterns are caller-owned; with validation on they are checked again right before use,
-  // so that arrays changed or released since plan creation are reported instead of read.
-  if (P->opt.validate) validate_patterns(P, s);
+  // The patterns are caller-owned; with validation 1 they are checked again right before use,
+  // so that arrays changed or released since plan creation are reported instead of read (2: the
+  // caller runs this right after creating the plan, whose check still holds).
+  if (P->opt.validate == 1) validate_patterns(P, s);
   // device counters read back together: [0] a scan total passed INT32_MAX, [1] rows of AP left
   // to the class launches, [2] rows of C left to them; [4..5] a scan's 64-bit total (copied)
   int* dflag = t.get<int>(8);

@@ -55,10 +55,12 @@ def test_counts_beyond_int32_rejected_without_gpu():
 
 def test_bad_options_rejected_without_gpu():
     """Option values out of range are PTAP_ERR_INPUT before any device call: an even hash
-    multiplier, an unknown owner kernel, a workgroup size other than 4, 8 or 16."""
+    multiplier, an unknown owner kernel, a workgroup size other than 4, 8 or 16, a validation
+    level other than 0, 1 or 2."""
     fake = ctypes.c_void_p(0x1000)
     L = lib.load_library()
-    for field, value in [("hash_mul", 2), ("hash_mul", 0x9E3779B0), ("owner_kernel", 2), ("owner_waves", 12)]:
+    for field, value in [("hash_mul", 2), ("hash_mul", 0x9E3779B0), ("owner_kernel", 2), ("owner_waves", 12),
+                         ("validate", 3), ("validate", -1)]:
         o = lib.ptap_options_default()
         setattr(o, field, value)
         h = ctypes.c_void_p()
